@@ -1,0 +1,82 @@
+"""The synthetic input generator: spectrum shape (estimator of Sect. 3.1.1),
+zero divergence, unit rms, determinism, and pool layout."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2604_11008_amd import gen
+
+
+@pytest.fixture(scope="module")
+def field64():
+    return gen.spectral_field(64, 4, 8, gen.seeds(0)[0])
+
+
+def test_unit_rms(field64):
+    ms = sum(float(np.mean(u * u)) for u in field64) / 3
+    assert abs(ms - 1.0) < 1e-12
+
+
+def test_deterministic(field64):
+    again = gen.spectral_field(64, 4, 8, gen.seeds(0)[0])
+    for a, b in zip(field64, again):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_divergence_free_in_spectral_space(field64):
+    n = 64
+    f = np.fft.fftfreq(n, d=1.0 / n)
+    kz, ky, kx = np.meshgrid(f, f, f, indexing="ij")
+    uh = [np.fft.fftn(u) for u in field64]
+    div = kx * uh[0] + ky * uh[1] + kz * uh[2]
+    mag = np.sqrt(kx ** 2 + ky ** 2 + kz ** 2) * np.sqrt(sum(np.abs(c) ** 2 for c in uh))
+    assert np.max(np.abs(div)) <= 1e-10 * np.max(mag)
+
+
+def test_spectrum_follows_the_model_shape(field64):
+    e = gen.shell_spectrum(field64, kmax_out=12)
+    model = gen.model_spectrum(np.arange(13), 4)
+    # shells 3..7 are complete (shell 8 is cut at |k| = 8)
+    ratio = e[3:8] / model[3:8]
+    assert np.max(np.abs(ratio / np.median(ratio) - 1)) < 0.15
+    assert np.all(e[9:] < 1e-20 * e.max())
+    # Parseval: half the mean square speed equals the summed shell energy up to
+    # the shell-weighting of the estimator
+    ke = 0.5 * sum(float(np.mean(u * u)) for u in field64)
+    assert 0.7 < e.sum() / ke < 1.4
+
+
+def test_pool_layout_and_canonical_order():
+    wl = gen.make_workload("C1", np_override=5000, n_override=32)
+    pool = wl.pool
+    assert np.all(np.diff(pool.base) >= 0)
+    assert np.all(pool.base[:-1] + pool.cap[:-1] <= pool.base[1:])
+    assert np.all(pool.count <= pool.cap)
+    ids = np.concatenate([pool.id[pool.segment(s)] for s in range(8)])
+    np.testing.assert_array_equal(np.sort(ids), np.arange(5000, dtype=np.uint64))
+    for s in range(8):
+        x = pool.x[:, pool.segment(s)]
+        assert np.all((x >= 0) & (x < wl.L))
+        np.testing.assert_array_equal(gen.owner(x, wl.bounds, wl.p), s)
+        cell = np.floor(x * (wl.n / wl.L)).astype(np.int64)
+        key = cell[0] + wl.n * (cell[1] + wl.n * cell[2])
+        assert np.all(np.diff(key) >= 0)
+
+
+def test_blob_and_lognormal_distributions():
+    g = gen.rng(gen.seeds(2)[1])
+    pos = gen.blob_positions(g, 100000, 64)
+    assert pos.shape == (3, 100000) and np.all((pos >= 0) & (pos < 2 * math.pi))
+    b = gen.bounds((4, 4, 4))
+    pos = gen.lognormal_positions(gen.rng(gen.seeds(3)[1]), (4, 4, 4), b, median=200)
+    s = gen.owner(pos, b, (4, 4, 4))
+    counts = np.bincount(s, minlength=64)
+    assert 100 < np.median(counts) < 400
+
+
+def test_tau_distributions():
+    g = gen.rng(1)
+    t = gen.draw_tau(g, 100000, ("loguniform", 0.01, 1.0))
+    assert t.min() >= 0.01 and t.max() <= 1.0
+    assert abs(np.median(np.log(t)) - math.log(0.1)) < 0.05
