@@ -1,0 +1,244 @@
+"""Benchmark of the fused particle step on one MI355X.
+
+Default workload (the 256^3 single-subdomain case): a 256^3 collocated FP64
+velocity field stored with a one-cell halo, 4,194,304 particles uniform in the
+box, tau log-uniform in [0.01, 1], gravity (0,0,-1), dt giving at most half a
+cell per step; one subdomain whose 26 neighbours are its own periodic images.
+
+A step is the whole hot path over every particle: interpolation at two RK2
+stages, the Heun drag update, classification, scan, pack/compact and the
+on-device append of the migrants.  Inputs are resident in HBM before the
+timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2604_11008_amd import gen  # noqa: E402  (seeded inputs; no torch)
+
+METRIC = "particles/sec per full step (interp+drag+scan-migrate); HBM GB/s; FP32 vs FP64"
+
+WORKLOADS = {
+    "C2": "256^3 FP64 field with a one-cell halo, 4,194,304 uniform particles, "
+          "1 subdomain (26 periodic self-neighbour buffers), tau log-uniform [0.01,1], "
+          "g=(0,0,-1), dt=0.5 cell/(max|u|+tau_max|g|)",
+    "C1": "64^3 periodic FP64 field, 65,536 uniform particles, 2x2x2 subdomains, dt=0.01",
+    "C2S": "256^3 periodic FP64 field, 4,194,304 uniform particles, 8x8x8 subdomains, "
+           "dt=0.5 cell per unit speed (a few percent migrate per step)",
+    "C3": "512^3 periodic FP64 field, 2^26 blob-clustered particles, 4x4x4 subdomains",
+    "C4": "512^3 periodic FP64 field, lognormal per-subdomain counts (median 1e5), "
+          "8x8x8 subdomains",
+    "C5": "1024^3 periodic FP32 field, 2^28 blob-clustered particles (FP64 positions, "
+          "FP32 velocity/tau), 8x8x8 subdomains",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
+    ap.add_argument("--tune", default=None, help="wg,items[,blocks_per_cu] or 'auto'")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain torch copy of 1 GiB (PMC scaling reference)")
+    ap.add_argument("--traffic", default=None,
+                    help="JSON with measured fetch/write bytes per fused launch")
+    ap.add_argument("--plain", action="store_true", help="time the 3-call plain path too")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, seconds):
+    """The oracle, single-threaded, on whole steps of the same workload."""
+    import oracle
+    pool = wl.pool
+    of = oracle.Field(wl.stored_field(np.float64), wl.n, wl.halo, wl.L)
+    od = oracle.Decomp(wl.p, wl.bounds)
+    sb, sc = gen.send_layout(pool.count, face=0.05, edge=0.01, corner=0.005)
+    npart = int(pool.count.sum())
+    done = 0
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        out = gen.empty_pool(pool.base, pool.cap)
+        send = gen.empty_pool(sb, sc)
+        oracle.step(of, od, wl.dt, wl.g, pool, out, send)
+        steps += 1
+        done += npart
+        if time.perf_counter() - t0 >= seconds or steps >= 8:
+            break
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} whole oracle step(s) of the same workload "
+                      f"({npart} particles each, sequential FP64, one thread), {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
+              "supported (subdomains are virtual partitions of one device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_11008_amd import accounting, pm
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    wl = gen.make_workload(args.config)
+    t_gen = time.perf_counter() - t_gen
+    mixed = wl.mode == "mixed"
+    fdt = np.float32 if mixed else np.float64
+    field = pm.DeviceField(wl.stored_field(fdt), wl.n, wl.halo, wl.L, device=dev)
+    dc = pm.Decomp(wl.p, wl.bounds)
+    vdt = torch.float32 if mixed else torch.float64
+    pool = wl.pool
+    npart = int(pool.count.sum())
+    size = pool.x.shape[1]
+    pa = pm.DevicePool.from_host(pool, dev)
+    pb = pm.DevicePool.empty(pool.base, pool.cap, vdtype=vdt, device=dev, size=size)
+    sb, sc = gen.send_layout(pool.count, face=0.05, edge=0.01, corner=0.005)
+    send = pm.DevicePool.empty(sb, sc, vdtype=vdt, device=dev)
+    ctx = pm.Context(size, send.size, dc.nsub, device=dev)
+    # v0 = U(x0), interpolated on the device
+    pa.v.copy_(ctx.interp(field, pa.x))
+    params = pm.Params(wl.dt, wl.g)
+    if args.tune == "auto":
+        ctx.autotune(field, dc, pa, pb, send, params,
+                     cache_path=os.path.join(ROOT, "profiles", "tune_cache.txt"))
+    elif args.tune:
+        t = [int(v) for v in args.tune.split(",")]
+        ctx.set_tuning(*t)
+    if args.graph:
+        ctx.set_graph(True)
+    torch.cuda.synchronize()
+    print(f"[bench] {args.config}: {npart} particles, field {wl.n}^3 halo={wl.halo}, "
+          f"{dc.nsub} subdomains, dt={wl.dt:.4g}, gen {t_gen:.1f}s, tuning {ctx.get_tuning()}",
+          file=sys.stderr, flush=True)
+
+    # warm-up
+    for _ in range(args.warmup):
+        ctx.step(field, dc, pa, pb, send, params)
+        pa, pb = pb, pa
+    f = ctx.get_status()
+    if f:
+        raise SystemExit(f"warm-up flags: {pm.flag_names(f)}")
+
+    # algorithmic bytes of a step of this state (untimed): touched field nodes
+    # and migrants
+    touched = ctx.touched_nodes(field, pa, params)
+    ctx.step(field, dc, pa, pb, send, params)
+    migrants = int(send.count.sum().item())
+    pa, pb = pb, pa
+    alg = accounting.step_algorithmic_bytes(npart, migrants, touched,
+                                            "mixed" if mixed else "f64")
+
+    # timed region
+    if not args.graph:
+        ctx.set_timing(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.step(field, dc, pa, pb, send, params)
+        pa, pb = pb, pa
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    f = ctx.get_status()
+    if f:
+        raise SystemExit(f"flags after timed steps: {pm.flag_names(f)}")
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    k_total, k_each = (ctx.kernel_times() if not args.graph else (None, []))
+    k_ms = (k_total / len(k_each)) if k_each else None
+    print(f"[bench] {args.steps} steps: {ms_step:.4f} ms/step; fused kernel "
+          f"{k_ms if k_ms is None else round(k_ms, 4)} ms", file=sys.stderr, flush=True)
+
+    roof = None
+    if k_ms:
+        achieved = alg["fused_kernel"] / (k_ms * 1e-3) / 1e9
+        traffic = None
+        if args.traffic and os.path.exists(args.traffic):
+            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+        roof = {"bound": "hbm", "achieved": round(achieved, 1),
+                "peak": accounting.HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / accounting.HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": "k_step (fused interpolate/advance/classify/scan/scatter)",
+                "kernel_ms": round(k_ms, 5),
+                "algorithmic_bytes_per_launch": alg["fused_kernel"]}
+
+    extra = {}
+    if args.plain:
+        ctx.set_timing(0)
+        sendp = pm.DevicePool.empty(sb, sc, vdtype=vdt, device=dev)
+        work = pm.DevicePool.empty(pool.base, pool.cap, vdtype=vdt, device=dev, size=size)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for _ in range(args.steps):
+            work.x.copy_(pa.x)
+            work.v.copy_(pa.v)
+            work.tau.copy_(pa.tau)
+            work.id.copy_(pa.id)
+            work.count.copy_(pa.count)
+            ctx.interp_advance(field, work, params)
+            ctx.classify_scan_pack(dc, work, sendp)
+            ctx.compact_append(dc, work, sendp, pb)
+        torch.cuda.synchronize()
+        tp1 = time.perf_counter()
+        extra["plain_ms_per_step_incl_copy"] = round((tp1 - tp0) * 1e3 / args.steps, 4)
+
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        cms = e0.elapsed_time(e1) / 10
+        extra["copy_1GiB_ms"] = round(cms, 4)
+        extra["copy_GBps"] = round(2 * a.numel() * 8 / (cms * 1e-3) / 1e9, 1)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+
+    value = npart / (ms_step * 1e-3)
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "particles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "mixed-f32/f64" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}",
+                   "particles": npart, "grid": wl.n, "halo": wl.halo,
+                   "subdomains": list(wl.p), "graph": bool(args.graph),
+                   "tuning": list(ctx.get_tuning())},
+        "hbm_GBps_algorithmic": round(alg["step"] / (ms_step * 1e-3) / 1e9, 1),
+        "algorithmic_bytes_per_step": alg["step"], "touched_nodes": touched,
+        "migrants_per_step": migrants,
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,261 @@
+/*
+ * pm.h -- C ABI of the MI355X (gfx950) Lagrangian particle step.
+ *
+ * Method: LCS.jl (Tominaga & Onishi, arXiv 2604.11008).  Each step moves
+ * every particle of a pool partitioned into subdomains:
+ *   1. U(X): trilinear interpolation of the fluid velocity from the eight
+ *      surrounding cell-centre values (Sect. 2.2, Particle Phase);
+ *   2. dX/dt = V, dV/dt = -(1/tau)(V - U(X)) + g, advanced with a two-stage
+ *      second-order Runge-Kutta method (Heun) (Sect. 2.2; drag factor f = 1);
+ *   3. the boundary-crossing check against the owner subdomain, generalised
+ *      from the paper's send/stay mask to 26 neighbour directions
+ *      (Sect. 2.3.3, stage 1);
+ *   4. a prefix scan of the 27 direction masks giving every particle a unique
+ *      slot (Sect. 2.3.3, stages 2-3: scan[i] = sum of mask[1..i]), packing
+ *      the leavers into per-direction send buffers and compacting the
+ *      stayers, then appending what every subdomain receives (unpacking,
+ *      Sect. 3.2.2).
+ * The subdomains are virtual partitions of one device's memory, so the
+ * exchange between them is an on-device copy.
+ *
+ * Conventions (where the paper is silent):
+ *   - node (i,j,k) of the field sits at the cell centre ((i+1/2)L/n, ...);
+ *   - ownership intervals are half-open: b[a] <= x < b[a+1];
+ *   - direction code d = 9(oz+1) + 3(oy+1) + (ox+1), o in {-1,0,1};
+ *     d == 13 (PM_STAY) means "no boundary crossed";
+ *   - subdomain index s = ax + Px*(ay + Py*az);
+ *   - the periodic shift is applied by the sender when it packs: x - L when
+ *     leaving through L, and x + L when leaving through 0, replaced by the
+ *     largest double below L if that sum rounds to L;
+ *   - stayers keep their order; received particles follow them, direction
+ *     code ascending, each send buffer in its own order;
+ *   - a particle that would move beyond its neighbour (PM_F_SKIP) or has a
+ *     non-finite coordinate (PM_F_NONFINITE) stays where it is.
+ *
+ * Memory: every array is device memory owned by the caller; the library
+ * never allocates device memory.  Pointers must stay valid until the work
+ * queued on the stream has finished.  Streams are hipStream_t values passed
+ * as void* (NULL = the null stream).  Every call is asynchronous except
+ * pm_get_status, pm_autotune and pm_kernel_times, which synchronise.
+ * A pm_ctx is not thread-safe: use one context per stream.
+ *
+ * Errors: argument errors are detected on the host and returned as
+ * PM_ERR_ARG before anything is queued (pm_last_error() tells why).  Errors
+ * found while running set bits in the context's device flag word, read (and
+ * cleared) by pm_get_status.  Capacity overflows still count exactly, so the
+ * counts written are the capacities that would have sufficed; records that
+ * did not fit are not written.  PM_F_LAYOUT (inconsistent segment tables)
+ * turns every later call of the context into a no-op until the flags are
+ * read and cleared, so that nothing is read or written out of bounds.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { PM_OK = 0, PM_ERR_ARG = 1, PM_ERR_HIP = 2 } pm_status;
+
+/* Element type of the field and of the particle velocities/tau.
+ * Two modes are supported:
+ *   field PM_F64 with particles PM_F64 (64-byte records), and
+ *   field PM_F32 with particles PM_F32 ("mixed": interpolation and drag in
+ *   float32, positions, their updates and all classification in float64;
+ *   48-byte records). */
+typedef enum { PM_F64 = 0, PM_F32 = 1 } pm_dtype;
+
+#define PM_STAY 13
+
+/* Device flag bits (pm_get_status). */
+#define PM_F_SEND_OVERFLOW 1u  /* a send buffer (s,d) was too small            */
+#define PM_F_DEST_OVERFLOW 2u  /* an output segment was too small              */
+#define PM_F_SKIP          4u  /* a particle moved beyond its neighbour        */
+#define PM_F_NONFINITE     8u  /* a position coordinate was NaN or +-inf       */
+#define PM_F_HALO          16u /* an interpolation stencil left the stored grid */
+#define PM_F_LAYOUT        32u /* count > cap, a segment beyond the pool extent
+                                  given to pm_create, or more tiles than the
+                                  workspace holds                               */
+
+/* Limits. */
+#define PM_MAX_P    32     /* subdomains per axis                             */
+#define PM_MAX_NSUB 4096   /* subdomains in total                             */
+
+/* Velocity field on a uniform grid over [0,L0)x[0,L1)x[0,L2).
+ * u[c] (c = x,y,z component) is a device array, x fastest:
+ *   halo == 0: n0*n1*n2 values, node indices taken modulo n (periodic);
+ *   halo == 1: (n0+2)(n1+2)(n2+2) values, stored index i+1 holds node i, so
+ *              stored 0 and n+1 are the halo nodes -1 and n (for a periodic
+ *              box: copies of nodes n-1 and 0). */
+typedef struct {
+    int32_t n[3];
+    int32_t halo;
+    double L[3];
+    int32_t dtype;      /* pm_dtype */
+    int32_t pad_;
+    const void *u[3];
+} pm_field;
+
+/* P0 x P1 x P2 subdomains.  bounds[a] is a HOST array of p[a]+1 strictly
+ * increasing doubles with bounds[a][0] == 0 and bounds[a][p[a]] == L, the
+ * very double used as the box side (also pm_field.L[a] where a field is
+ * given).  The values are copied into the launch; the arrays need not
+ * outlive the call. */
+typedef struct {
+    int32_t p[3];
+    int32_t pad_;
+    const double *bounds[3];
+} pm_decomp;
+
+/* A pool of particle records (structure of arrays, device memory), cut
+ * into nsub segments: segment s occupies records [base[s], base[s]+cap[s])
+ * and holds count[s] particles at its start.  base/cap/count are device
+ * int64 arrays of nsub entries.  x[c] are float64; v[c] and tau are of type
+ * vdtype; id is uint64.  Segments must not overlap and must end within the
+ * pool extent given to pm_create. */
+typedef struct {
+    int32_t nsub;
+    int32_t vdtype;     /* pm_dtype */
+    const int64_t *base;
+    const int64_t *cap;
+    int64_t *count;
+    double *x[3];
+    void *v[3];
+    void *tau;
+    uint64_t *id;
+} pm_particles;
+
+/* Send buffers: segment s*27+d holds what subdomain s sends in direction d
+ * (the d == PM_STAY segments are unused and may have cap 0).  Same record
+ * layout and vdtype as the particle pools; positions are stored already
+ * shifted into the receiver's periodic image. */
+typedef struct {
+    const int64_t *base;   /* device [nsub*27] */
+    const int64_t *cap;    /* device [nsub*27] */
+    int64_t *count;        /* device [nsub*27], written */
+    double *x[3];
+    void *v[3];
+    void *tau;
+    uint64_t *id;
+} pm_sendbufs;
+
+/* Time step and constant body force (gravity) added to dV/dt. */
+typedef struct {
+    double dt;
+    double g[3];
+} pm_params;
+
+/* Launch shape of the tile kernels: workgroup size (256 or 512), records
+ * per thread (1, 2, 4 or 8); tile = wg*items records.  blocks_per_cu is the
+ * persistent grid's workgroups per compute unit (0 = as many as fit). */
+typedef struct {
+    int32_t wg;
+    int32_t items;
+    int32_t blocks_per_cu;
+    int32_t pad_;
+} pm_tuning;
+
+typedef struct pm_ctx pm_ctx;
+
+/* Bytes of device workspace a context needs for pools of at most
+ * pool_extent records (max over segments of base+cap) and nsub subdomains. */
+size_t pm_workspace_bytes(int64_t pool_extent, int32_t nsub);
+
+/* Create a context on the current device.  workspace: caller-owned device
+ * memory of at least pm_workspace_bytes(pool_extent, nsub) bytes, 256-byte
+ * aligned; send_extent: max over send segments of base+cap.  Synchronous. */
+pm_status pm_create(pm_ctx **ctx, void *workspace, size_t ws_bytes,
+                    int64_t pool_extent, int64_t send_extent, int32_t nsub);
+pm_status pm_destroy(pm_ctx *ctx);
+
+/* U at n points (x,y,z device float64 arrays) into ux,uy,uz (device arrays
+ * of the field's dtype).  Sect. 2.2 (trilinear interpolation). */
+pm_status pm_interp(pm_ctx *ctx, const pm_field *field, int64_t n,
+                    const double *x, const double *y, const double *z,
+                    void *ux, void *uy, void *uz, void *stream);
+
+/* Steps 1-2 in place on the particles of segments [sub_first,
+ * sub_first+sub_count): X and V are replaced by the Heun update.
+ * Sect. 2.2 (particle ODE, two-stage second-order RK). */
+pm_status pm_interp_advance(pm_ctx *ctx, const pm_field *field,
+                            pm_particles *inout, const pm_params *params,
+                            int32_t sub_first, int32_t sub_count, void *stream);
+
+/* Steps 3-4 (mask, scan, pack) for segments [sub_first, sub_first+sub_count)
+ * of `in` (left unchanged): writes every leaver to send segment s*27+d at
+ * its scan slot, send->count for those segments, and each stayer's slot into
+ * the workspace for pm_compact_append.  Sect. 2.3.3 (stages 1-3). */
+pm_status pm_classify_scan_pack(pm_ctx *ctx, const pm_decomp *decomp,
+                                const pm_particles *in, pm_sendbufs *send,
+                                int32_t sub_first, int32_t sub_count,
+                                void *stream);
+
+/* Unpacking for destination segments [sub_first, sub_first+sub_count):
+ * the stayers of `in` compacted in order into `out`, then the particles
+ * sent to each destination appended; writes out->count.  Needs
+ * pm_classify_scan_pack to have run on these segments and on every
+ * subdomain that neighbours them, with no other classify call in between.
+ * Sect. 3.2.2 (unpacking: compaction, then receive). */
+pm_status pm_compact_append(pm_ctx *ctx, const pm_decomp *decomp,
+                            const pm_particles *in, const pm_sendbufs *send,
+                            pm_particles *out, int32_t sub_first,
+                            int32_t sub_count, void *stream);
+
+/* The whole step in -> out for all subdomains, fused into one persistent
+ * launch plus the on-device exchange; `in` is left unchanged.  Results are
+ * bitwise equal to pm_interp_advance (on a copy of in), then
+ * pm_classify_scan_pack, then pm_compact_append, over all subdomains.
+ * With graphs enabled (pm_set_graph) the launches are captured once per
+ * distinct argument set and replayed. */
+pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
+                  const pm_particles *in, pm_particles *out,
+                  pm_sendbufs *send, const pm_params *params, void *stream);
+
+/* Synchronise `stream`, return the flag word (PM_F_*) and clear it. */
+pm_status pm_get_status(pm_ctx *ctx, void *stream, uint32_t *flags);
+
+pm_status pm_set_tuning(pm_ctx *ctx, const pm_tuning *t);
+pm_status pm_get_tuning(pm_ctx *ctx, pm_tuning *t);
+
+/* Time every supported launch shape on this problem with pm_step (eager),
+ * keep the fastest in the context and, if cache_path is not NULL, append
+ * it to that text file keyed by the problem's shape.  Results do not
+ * depend on the launch shape.  Synchronous; in is unchanged, out and send
+ * are overwritten. */
+pm_status pm_autotune(pm_ctx *ctx, const pm_field *field,
+                      const pm_decomp *decomp, const pm_particles *in,
+                      pm_particles *out, pm_sendbufs *send,
+                      const pm_params *params, void *stream,
+                      const char *cache_path);
+
+/* Capture pm_step into HIP graphs (enable != 0) or launch eagerly. */
+pm_status pm_set_graph(pm_ctx *ctx, int32_t enable);
+
+/* Kernel timing: with max_records > 0, every eager pm_step records HIP
+ * events around its fused kernel on the caller's stream (up to max_records
+ * steps; 0 turns it off and drops the records).  pm_kernel_times
+ * synchronises and returns the number of recorded launches and the total
+ * and per-launch milliseconds (ms may be NULL). */
+pm_status pm_set_timing(pm_ctx *ctx, int32_t max_records);
+pm_status pm_kernel_times(pm_ctx *ctx, int32_t *n, double *total_ms, float *ms,
+                          int32_t max_ms);
+
+/* Untimed diagnostic: number of distinct field nodes read by the stage-1
+ * and stage-2 stencils of one pm_step from `in` (an exact count, through a
+ * bitmap of nbits >= number of stored nodes bits, caller-owned device
+ * memory of (nbits+63)/64 uint64, cleared here).  Synchronous. */
+pm_status pm_touched_nodes(pm_ctx *ctx, const pm_field *field,
+                           const pm_particles *in, const pm_params *params,
+                           uint64_t *bitmap, int64_t nbits, void *stream,
+                           int64_t *touched);
+
+/* Text of the last host-side error of this thread. */
+const char *pm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PM_H */

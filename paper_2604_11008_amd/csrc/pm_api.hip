@@ -1,0 +1,778 @@
+// pm_api.hip -- host side of the C ABI declared in include/pm.h: argument
+// checks, workspace layout, launch configuration, HIP-graph capture of the
+// fused step, kernel timing and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+pm_status arg_error(const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return PM_ERR_ARG;
+}
+
+pm_status hip_error(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return PM_ERR_HIP;
+}
+
+#define PM_HIP(call, what)                       \
+    do {                                         \
+        hipError_t e_ = (call);                  \
+        if (e_ != hipSuccess)                    \
+            return hip_error(e_, what);          \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct WsLayout {
+    size_t hdr, tile_start, stay, lb, slot, total;
+    int64_t max_tiles;
+};
+
+WsLayout ws_layout(int64_t pool_extent, int32_t nsub)
+{
+    WsLayout L{};
+    size_t o = 0;
+    L.hdr = o;
+    o += align256(pm::kHdrWords * sizeof(uint32_t));
+    L.tile_start = o;
+    o += align256((PM_MAX_NSUB + 1) * sizeof(int64_t));
+    L.stay = o;
+    o += align256((size_t)std::max(nsub, 1) * sizeof(int64_t));
+    L.max_tiles = pool_extent / pm::kMinTile + nsub + 2;
+    L.lb = o;
+    o += align256((size_t)L.max_tiles * pm::kLbWords * sizeof(uint64_t));
+    L.slot = o;
+    o += align256((size_t)std::max<int64_t>(pool_extent, 1) * sizeof(uint32_t));
+    L.total = o;
+    return L;
+}
+
+struct GraphEntry {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct pm_ctx {
+    int device = 0;
+    int cus = 0;
+    pm::DWS ws{};
+    int32_t nsub_max = 0;
+    pm::Shape shape{256, 4};
+    int blocks_per_cu = 0;
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    std::vector<GraphEntry> graphs;
+    int32_t tmax = 0;
+    int32_t tcount = 0;
+    std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// argument conversion
+// ---------------------------------------------------------------------------
+
+pm_status conv_field(const pm_field *f, pm::DField &d, bool &mixed)
+{
+    if (!f)
+        return arg_error("field is NULL");
+    if (f->halo != 0 && f->halo != 1)
+        return arg_error("field.halo must be 0 or 1");
+    if (f->dtype != PM_F64 && f->dtype != PM_F32)
+        return arg_error("field.dtype must be PM_F64 or PM_F32");
+    for (int a = 0; a < 3; ++a) {
+        if (f->n[a] < 2 || f->n[a] > (1 << 20))
+            return arg_error("field.n[%d] = %d out of range", a, f->n[a]);
+        if (!(f->L[a] > 0.0) || !std::isfinite(f->L[a]))
+            return arg_error("field.L[%d] must be positive and finite", a);
+        if (!f->u[a])
+            return arg_error("field.u[%d] is NULL", a);
+    }
+    const int64_t sx = f->n[0] + 2 * f->halo, sy = f->n[1] + 2 * f->halo,
+                  sz = f->n[2] + 2 * f->halo;
+    if (sx * sy * sz > (int64_t)1 << 40)
+        return arg_error("field too large");
+    for (int a = 0; a < 3; ++a) {
+        d.u[a] = f->u[a];
+        d.n[a] = f->n[a];
+        d.r[a] = (double)f->n[a] / f->L[a];
+    }
+    d.halo = f->halo;
+    d.sx = sx;
+    d.sxy = sx * sy;
+    mixed = f->dtype == PM_F32;
+    return PM_OK;
+}
+
+pm_status conv_decomp(const pm_decomp *dc, const double *Lfield, pm::DDecomp &d)
+{
+    if (!dc)
+        return arg_error("decomp is NULL");
+    int64_t nsub = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int P = dc->p[a];
+        if (P < 1 || P > PM_MAX_P)
+            return arg_error("decomp.p[%d] = %d not in 1..%d", a, P, PM_MAX_P);
+        if (!dc->bounds[a])
+            return arg_error("decomp.bounds[%d] is NULL", a);
+        const double *b = dc->bounds[a];
+        if (b[0] != 0.0)
+            return arg_error("decomp.bounds[%d][0] must be 0", a);
+        for (int k = 0; k < P; ++k)
+            if (!(b[k] < b[k + 1]) || !std::isfinite(b[k + 1]))
+                return arg_error("decomp.bounds[%d] must increase strictly", a);
+        if (Lfield && b[P] != Lfield[a])
+            return arg_error("decomp.bounds[%d][%d] must equal field.L[%d]", a, P, a);
+        d.p[a] = P;
+        for (int k = 0; k <= PM_MAX_P; ++k)
+            d.b[a][k] = k <= P ? b[k] : b[P];
+        d.L[a] = b[P];
+        d.predL[a] = std::nextafter(b[P], 0.0);
+        nsub *= P;
+    }
+    if (nsub > PM_MAX_NSUB)
+        return arg_error("%lld subdomains exceed %d", (long long)nsub, PM_MAX_NSUB);
+    d.nsub = (int32_t)nsub;
+    return PM_OK;
+}
+
+pm_status conv_pool(const pm_particles *p, const char *name, bool mixed, pm::DPool &d)
+{
+    if (!p)
+        return arg_error("%s is NULL", name);
+    if (p->vdtype != (mixed ? PM_F32 : PM_F64))
+        return arg_error("%s.vdtype must be %s with a %s field", name,
+                         mixed ? "PM_F32" : "PM_F64", mixed ? "PM_F32" : "PM_F64");
+    if (!p->base || !p->cap || !p->count || !p->tau || !p->id)
+        return arg_error("%s has a NULL array", name);
+    for (int a = 0; a < 3; ++a)
+        if (!p->x[a] || !p->v[a])
+            return arg_error("%s has a NULL array", name);
+    d.base = p->base;
+    d.cap = p->cap;
+    d.count = p->count;
+    for (int a = 0; a < 3; ++a) {
+        d.x[a] = p->x[a];
+        d.v[a] = p->v[a];
+    }
+    d.tau = p->tau;
+    d.id = p->id;
+    return PM_OK;
+}
+
+pm_status conv_send(const pm_sendbufs *s, pm::DPool &d)
+{
+    if (!s)
+        return arg_error("send is NULL");
+    if (!s->base || !s->cap || !s->count || !s->tau || !s->id)
+        return arg_error("send has a NULL array");
+    for (int a = 0; a < 3; ++a)
+        if (!s->x[a] || !s->v[a])
+            return arg_error("send has a NULL array");
+    d.base = s->base;
+    d.cap = s->cap;
+    d.count = s->count;
+    for (int a = 0; a < 3; ++a) {
+        d.x[a] = s->x[a];
+        d.v[a] = s->v[a];
+    }
+    d.tau = s->tau;
+    d.id = s->id;
+    return PM_OK;
+}
+
+pm_status conv_params(const pm_params *pr, pm::KArgs &k)
+{
+    if (!pr)
+        return arg_error("params is NULL");
+    if (!std::isfinite(pr->dt) || !std::isfinite(pr->g[0]) || !std::isfinite(pr->g[1]) ||
+        !std::isfinite(pr->g[2]))
+        return arg_error("params must be finite");
+    k.dt = pr->dt;
+    k.half_dt = 0.5 * pr->dt;
+    k.dtf = (float)pr->dt;
+    k.half_dtf = (float)(0.5 * pr->dt);
+    for (int c = 0; c < 3; ++c) {
+        k.g[c] = pr->g[c];
+        k.gf[c] = (float)pr->g[c];
+    }
+    return PM_OK;
+}
+
+pm_status check_range(pm_ctx *ctx, int32_t nsub, int32_t first, int32_t count)
+{
+    if (nsub < 1 || nsub > ctx->nsub_max)
+        return arg_error("nsub = %d not in 1..%d (context limit)", nsub, ctx->nsub_max);
+    if (first < 0 || count < 0 || (int64_t)first + count > nsub)
+        return arg_error("segment range [%d, %d) outside 0..%d", first, first + count, nsub);
+    return PM_OK;
+}
+
+int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed)
+{
+    const int occ = pm::step_occupancy(sh, mixed);
+    const int per = ctx->blocks_per_cu > 0 ? std::min(ctx->blocks_per_cu, occ) : occ;
+    return std::max(1, ctx->cus * per);
+}
+
+int append_cpt(int32_t count) { return std::max(1, 2048 / std::max(1, count)); }
+
+// Queue the fused step (prep, fused kernel, exchange) on `st`.
+pm_status queue_step(pm_ctx *ctx, pm::KArgs &k, bool mixed, hipStream_t st, bool timed)
+{
+    k.tile = ctx->shape.wg * ctx->shape.items;
+    k.cpt = append_cpt(k.sub_count);
+    PM_HIP(pm::launch_prep(k,
+                           pm::kPrepTiles | pm::kPrepZeroLb | pm::kPrepZeroCounts |
+                               pm::kPrepCheckIn | pm::kPrepCheckOut | pm::kPrepCheckSend,
+                           st),
+           "prep launch");
+    if (timed)
+        PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount], st), "event record");
+    PM_HIP(pm::launch_step(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed), st),
+           "fused step launch");
+    if (timed) {
+        PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount + 1], st), "event record");
+        ctx->tcount++;
+    }
+    const int grid = std::min(4096, k.sub_count * k.cpt);
+    PM_HIP(pm::launch_append(k, mixed, std::max(1, grid), st), "append launch");
+    return PM_OK;
+}
+
+void base_args(pm_ctx *ctx, pm::KArgs &k)
+{
+    std::memset(&k, 0, sizeof k);
+    k.ws = ctx->ws;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+const char *pm_last_error(void) { return g_err.c_str(); }
+
+size_t pm_workspace_bytes(int64_t pool_extent, int32_t nsub)
+{
+    if (pool_extent < 0 || nsub < 1)
+        return 0;
+    return ws_layout(pool_extent, nsub).total;
+}
+
+pm_status pm_create(pm_ctx **out, void *workspace, size_t ws_bytes, int64_t pool_extent,
+                    int64_t send_extent, int32_t nsub)
+{
+    if (!out)
+        return arg_error("ctx pointer is NULL");
+    *out = nullptr;
+    if (nsub < 1 || nsub > PM_MAX_NSUB)
+        return arg_error("nsub = %d not in 1..%d", nsub, PM_MAX_NSUB);
+    if (pool_extent < 0 || pool_extent > ((int64_t)1 << 34) || send_extent < 0)
+        return arg_error("pool or send extent out of range");
+    const WsLayout L = ws_layout(pool_extent, nsub);
+    if (!workspace || ws_bytes < L.total)
+        return arg_error("workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                         L.total);
+    if (((uintptr_t)workspace & 255u) != 0)
+        return arg_error("workspace must be 256-byte aligned");
+    pm_ctx *ctx = new pm_ctx();
+    PM_HIP(hipGetDevice(&ctx->device), "hipGetDevice");
+    PM_HIP(hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device),
+           "device attribute");
+    char *w = (char *)workspace;
+    ctx->ws.hdr = (uint32_t *)(w + L.hdr);
+    ctx->ws.tile_start = (int64_t *)(w + L.tile_start);
+    ctx->ws.stay = (int64_t *)(w + L.stay);
+    ctx->ws.lb = (uint64_t *)(w + L.lb);
+    ctx->ws.slot = (uint32_t *)(w + L.slot);
+    ctx->ws.max_tiles = L.max_tiles;
+    ctx->ws.pool_extent = pool_extent;
+    ctx->ws.send_extent = send_extent;
+    ctx->nsub_max = nsub;
+    // start from a clean header, tile table and look-back state
+    PM_HIP(hipMemset(workspace, 0, L.lb + (size_t)L.max_tiles * pm::kLbWords * sizeof(uint64_t)),
+           "workspace clear");
+    PM_HIP(hipDeviceSynchronize(), "workspace clear");
+    *out = ctx;
+    return PM_OK;
+}
+
+pm_status pm_destroy(pm_ctx *ctx)
+{
+    if (!ctx)
+        return PM_OK;
+    for (auto &g : ctx->graphs)
+        (void)hipGraphExecDestroy(g.exec);
+    for (auto e : ctx->events)
+        (void)hipEventDestroy(e);
+    if (ctx->cap_stream)
+        (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return PM_OK;
+}
+
+pm_status pm_interp(pm_ctx *ctx, const pm_field *field, int64_t n, const double *x,
+                    const double *y, const double *z, void *ux, void *uy, void *uz,
+                    void *stream)
+{
+    if (!ctx)
+        return arg_error("ctx is NULL");
+    pm::KArgs k;
+    base_args(ctx, k);
+    bool mixed = false;
+    pm_status s = conv_field(field, k.f, mixed);
+    if (s)
+        return s;
+    if (n < 0)
+        return arg_error("n < 0");
+    if (n == 0)
+        return PM_OK;
+    if (!x || !y || !z || !ux || !uy || !uz)
+        return arg_error("NULL array");
+    PM_HIP(pm::launch_interp(k, mixed, n, x, y, z, ux, uy, uz, (hipStream_t)stream),
+           "interp launch");
+    return PM_OK;
+}
+
+pm_status pm_interp_advance(pm_ctx *ctx, const pm_field *field, pm_particles *inout,
+                            const pm_params *params, int32_t sub_first, int32_t sub_count,
+                            void *stream)
+{
+    if (!ctx)
+        return arg_error("ctx is NULL");
+    pm::KArgs k;
+    base_args(ctx, k);
+    bool mixed = false;
+    pm_status s = conv_field(field, k.f, mixed);
+    if (!s)
+        s = conv_pool(inout, "inout", mixed, k.in);
+    if (!s)
+        s = conv_params(params, k);
+    if (!s)
+        s = check_range(ctx, inout->nsub, sub_first, sub_count);
+    if (s)
+        return s;
+    if (sub_count == 0)
+        return PM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    k.sub_first = sub_first;
+    k.sub_count = sub_count;
+    k.tile = ctx->shape.wg * ctx->shape.items;
+    PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn, st), "prep launch");
+    PM_HIP(pm::launch_advance(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed), st),
+           "advance launch");
+    return PM_OK;
+}
+
+pm_status pm_classify_scan_pack(pm_ctx *ctx, const pm_decomp *decomp, const pm_particles *in,
+                                pm_sendbufs *send, int32_t sub_first, int32_t sub_count,
+                                void *stream)
+{
+    if (!ctx)
+        return arg_error("ctx is NULL");
+    pm::KArgs k;
+    base_args(ctx, k);
+    pm_status s = conv_decomp(decomp, nullptr, k.dc);
+    if (s)
+        return s;
+    if (!in)
+        return arg_error("in is NULL");
+    const bool mixed = in->vdtype == PM_F32;
+    s = conv_pool(in, "in", mixed, k.in);
+    if (!s)
+        s = conv_send(send, k.send);
+    if (!s)
+        s = check_range(ctx, in->nsub, sub_first, sub_count);
+    if (!s && in->nsub != k.dc.nsub)
+        s = arg_error("in.nsub = %d but the decomposition has %d subdomains", in->nsub,
+                      k.dc.nsub);
+    if (s)
+        return s;
+    if (sub_count == 0)
+        return PM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    k.sub_first = sub_first;
+    k.sub_count = sub_count;
+    k.tile = ctx->shape.wg * ctx->shape.items;
+    PM_HIP(pm::launch_prep(k,
+                           pm::kPrepTiles | pm::kPrepZeroLb | pm::kPrepZeroCounts |
+                               pm::kPrepCheckIn | pm::kPrepCheckSend,
+                           st),
+           "prep launch");
+    PM_HIP(pm::launch_classify(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed), st),
+           "classify launch");
+    return PM_OK;
+}
+
+pm_status pm_compact_append(pm_ctx *ctx, const pm_decomp *decomp, const pm_particles *in,
+                            const pm_sendbufs *send, pm_particles *out, int32_t sub_first,
+                            int32_t sub_count, void *stream)
+{
+    if (!ctx)
+        return arg_error("ctx is NULL");
+    pm::KArgs k;
+    base_args(ctx, k);
+    pm_status s = conv_decomp(decomp, nullptr, k.dc);
+    if (s)
+        return s;
+    if (!in)
+        return arg_error("in is NULL");
+    const bool mixed = in->vdtype == PM_F32;
+    s = conv_pool(in, "in", mixed, k.in);
+    if (!s)
+        s = conv_pool(out, "out", mixed, k.out);
+    if (!s)
+        s = conv_send(send, k.send);
+    if (!s)
+        s = check_range(ctx, in->nsub, sub_first, sub_count);
+    if (!s && (in->nsub != k.dc.nsub || out->nsub != k.dc.nsub))
+        s = arg_error("pool nsub does not match the decomposition (%d)", k.dc.nsub);
+    if (s)
+        return s;
+    if (sub_count == 0)
+        return PM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    k.sub_first = sub_first;
+    k.sub_count = sub_count;
+    k.tile = ctx->shape.wg * ctx->shape.items;
+    k.cpt = append_cpt(sub_count);
+    PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn | pm::kPrepCheckOut |
+                                  pm::kPrepCheckSend,
+                           st),
+           "prep launch");
+    PM_HIP(pm::launch_compact(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed), st),
+           "compact launch");
+    const int grid = std::min(4096, sub_count * k.cpt);
+    PM_HIP(pm::launch_append(k, mixed, std::max(1, grid), st), "append launch");
+    return PM_OK;
+}
+
+static pm_status step_args(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
+                           const pm_particles *in, pm_particles *out, pm_sendbufs *send,
+                           const pm_params *params, pm::KArgs &k, bool &mixed)
+{
+    if (!ctx)
+        return arg_error("ctx is NULL");
+    base_args(ctx, k);
+    pm_status s = conv_field(field, k.f, mixed);
+    if (!s)
+        s = conv_decomp(decomp, field->L, k.dc);
+    if (!s)
+        s = conv_pool(in, "in", mixed, k.in);
+    if (!s)
+        s = conv_pool(out, "out", mixed, k.out);
+    if (!s)
+        s = conv_send(send, k.send);
+    if (!s)
+        s = conv_params(params, k);
+    if (!s && (in->nsub != k.dc.nsub || out->nsub != k.dc.nsub))
+        s = arg_error("pool nsub does not match the decomposition (%d)", k.dc.nsub);
+    if (!s)
+        s = check_range(ctx, in->nsub, 0, in->nsub);
+    if (s)
+        return s;
+    if (in->x[0] == out->x[0])
+        return arg_error("pm_step is out of place: in and out must differ");
+    k.sub_first = 0;
+    k.sub_count = in->nsub;
+    return PM_OK;
+}
+
+pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
+                  const pm_particles *in, pm_particles *out, pm_sendbufs *send,
+                  const pm_params *params, void *stream)
+{
+    pm::KArgs k;
+    bool mixed = false;
+    pm_status s = step_args(ctx, field, decomp, in, out, send, params, k, mixed);
+    if (s)
+        return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (!ctx->use_graph) {
+        const bool timed = ctx->tmax > 0 && ctx->tcount < ctx->tmax;
+        return queue_step(ctx, k, mixed, st, timed);
+    }
+    // graph path: one captured graph per distinct argument set and shape
+    k.tile = ctx->shape.wg * ctx->shape.items;
+    k.cpt = append_cpt(k.sub_count);
+    std::vector<unsigned char> key(sizeof k + sizeof ctx->shape + sizeof(int));
+    std::memcpy(key.data(), &k, sizeof k);
+    std::memcpy(key.data() + sizeof k, &ctx->shape, sizeof ctx->shape);
+    std::memcpy(key.data() + sizeof k + sizeof ctx->shape, &ctx->blocks_per_cu, sizeof(int));
+    for (auto &g : ctx->graphs)
+        if (g.key == key) {
+            PM_HIP(hipGraphLaunch(g.exec, st), "graph launch");
+            return PM_OK;
+        }
+    if (!ctx->cap_stream)
+        PM_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "stream create");
+    PM_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal),
+           "begin capture");
+    pm_status qs = queue_step(ctx, k, mixed, ctx->cap_stream, false);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (qs)
+        return qs;
+    if (ce != hipSuccess)
+        return hip_error(ce, "end capture");
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess)
+        return hip_error(ie, "graph instantiate");
+    if (ctx->graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back({key, exec});
+    PM_HIP(hipGraphLaunch(exec, st), "graph launch");
+    return PM_OK;
+}
+
+pm_status pm_get_status(pm_ctx *ctx, void *stream, uint32_t *flags)
+{
+    if (!ctx || !flags)
+        return arg_error("NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    PM_HIP(hipStreamSynchronize(st), "stream sync");
+    uint32_t f = 0;
+    PM_HIP(hipMemcpy(&f, ctx->ws.hdr + pm::kHdrFlags, sizeof f, hipMemcpyDeviceToHost),
+           "status read");
+    const uint32_t zero = 0;
+    PM_HIP(hipMemcpy(ctx->ws.hdr + pm::kHdrFlags, &zero, sizeof zero, hipMemcpyHostToDevice),
+           "status clear");
+    *flags = f;
+    return PM_OK;
+}
+
+pm_status pm_set_tuning(pm_ctx *ctx, const pm_tuning *t)
+{
+    if (!ctx || !t)
+        return arg_error("NULL argument");
+    const pm::Shape sh{t->wg, t->items};
+    if (!pm::shape_supported(sh))
+        return arg_error("launch shape wg=%d items=%d is not built", t->wg, t->items);
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 32)
+        return arg_error("blocks_per_cu out of range");
+    ctx->shape = sh;
+    ctx->blocks_per_cu = t->blocks_per_cu;
+    return PM_OK;
+}
+
+pm_status pm_get_tuning(pm_ctx *ctx, pm_tuning *t)
+{
+    if (!ctx || !t)
+        return arg_error("NULL argument");
+    t->wg = ctx->shape.wg;
+    t->items = ctx->shape.items;
+    t->blocks_per_cu = ctx->blocks_per_cu;
+    t->pad_ = 0;
+    return PM_OK;
+}
+
+pm_status pm_set_graph(pm_ctx *ctx, int32_t enable)
+{
+    if (!ctx)
+        return arg_error("ctx is NULL");
+    ctx->use_graph = enable != 0;
+    return PM_OK;
+}
+
+pm_status pm_set_timing(pm_ctx *ctx, int32_t max_records)
+{
+    if (!ctx)
+        return arg_error("ctx is NULL");
+    if (max_records < 0 || max_records > (1 << 16))
+        return arg_error("max_records out of range");
+    for (auto e : ctx->events)
+        (void)hipEventDestroy(e);
+    ctx->events.clear();
+    ctx->tcount = 0;
+    ctx->tmax = max_records;
+    for (int i = 0; i < 2 * max_records; ++i) {
+        hipEvent_t e;
+        PM_HIP(hipEventCreate(&e), "event create");
+        ctx->events.push_back(e);
+    }
+    return PM_OK;
+}
+
+pm_status pm_kernel_times(pm_ctx *ctx, int32_t *n, double *total_ms, float *ms, int32_t max_ms)
+{
+    if (!ctx || !n || !total_ms)
+        return arg_error("NULL argument");
+    double tot = 0.0;
+    for (int i = 0; i < ctx->tcount; ++i) {
+        PM_HIP(hipEventSynchronize(ctx->events[2 * i + 1]), "event sync");
+        float t = 0.f;
+        PM_HIP(hipEventElapsedTime(&t, ctx->events[2 * i], ctx->events[2 * i + 1]), "elapsed");
+        tot += t;
+        if (ms && i < max_ms)
+            ms[i] = t;
+    }
+    *n = ctx->tcount;
+    *total_ms = tot;
+    return PM_OK;
+}
+
+pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
+                      const pm_particles *in, pm_particles *out, pm_sendbufs *send,
+                      const pm_params *params, void *stream, const char *cache_path)
+{
+    pm::KArgs k;
+    bool mixed = false;
+    pm_status s = step_args(ctx, field, decomp, in, out, send, params, k, mixed);
+    if (s)
+        return s;
+    hipStream_t st = (hipStream_t)stream;
+    char key[256];
+    snprintf(key, sizeof key, "n=%d,%d,%d halo=%d dtype=%d nsub=%d extent=%lld",
+             field->n[0], field->n[1], field->n[2], field->halo, field->dtype, k.dc.nsub,
+             (long long)ctx->ws.pool_extent);
+    if (cache_path) {
+        if (FILE *fp = fopen(cache_path, "r")) {
+            char line[512];
+            int wg = 0, items = 0, bpc = 0;
+            bool hit = false;
+            while (fgets(line, sizeof line, fp)) {
+                char *bar = strchr(line, '|');
+                if (!bar)
+                    continue;
+                *bar = 0;
+                if (strcmp(line, key) == 0 &&
+                    sscanf(bar + 1, " wg=%d items=%d bpc=%d", &wg, &items, &bpc) == 3) {
+                    hit = true;
+                }
+            }
+            fclose(fp);
+            if (hit && pm::shape_supported({wg, items})) {
+                ctx->shape = {wg, items};
+                ctx->blocks_per_cu = bpc;
+                return PM_OK;
+            }
+        }
+    }
+    const pm::Shape shapes[] = {{256, 1}, {256, 2}, {256, 4}, {256, 8},
+                                {512, 1}, {512, 2}, {512, 4}};
+    const int bpcs[] = {0, 1, 2};
+    const bool was_graph = ctx->use_graph;
+    const int32_t was_tmax = ctx->tmax;
+    ctx->use_graph = false;
+    ctx->tmax = 0;
+    hipEvent_t e0, e1;
+    PM_HIP(hipEventCreate(&e0), "event create");
+    PM_HIP(hipEventCreate(&e1), "event create");
+    float best = 1e30f;
+    pm::Shape best_sh = ctx->shape;
+    int best_bpc = ctx->blocks_per_cu;
+    for (const auto &sh : shapes) {
+        for (int bpc : bpcs) {
+            if (bpc > pm::step_occupancy(sh, mixed))
+                continue;
+            ctx->shape = sh;
+            ctx->blocks_per_cu = bpc;
+            pm::KArgs kk = k;
+            pm_status r = PM_OK;
+            for (int it = 0; it < 2 && !r; ++it)
+                r = queue_step(ctx, kk, mixed, st, false);
+            PM_HIP(hipEventRecord(e0, st), "event record");
+            const int reps = 5;
+            for (int it = 0; it < reps && !r; ++it)
+                r = queue_step(ctx, kk, mixed, st, false);
+            PM_HIP(hipEventRecord(e1, st), "event record");
+            PM_HIP(hipEventSynchronize(e1), "event sync");
+            if (r)
+                return r;
+            float ms = 0.f;
+            PM_HIP(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            ms /= reps;
+            if (ms < best) {
+                best = ms;
+                best_sh = sh;
+                best_bpc = bpc;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->shape = best_sh;
+    ctx->blocks_per_cu = best_bpc;
+    ctx->use_graph = was_graph;
+    ctx->tmax = was_tmax;
+    if (cache_path) {
+        if (FILE *fp = fopen(cache_path, "a")) {
+            fprintf(fp, "%s| wg=%d items=%d bpc=%d ms=%.4f\n", key, best_sh.wg, best_sh.items,
+                    best_bpc, best);
+            fclose(fp);
+        }
+    }
+    return PM_OK;
+}
+
+pm_status pm_touched_nodes(pm_ctx *ctx, const pm_field *field, const pm_particles *in,
+                           const pm_params *params, uint64_t *bitmap, int64_t nbits,
+                           void *stream, int64_t *touched)
+{
+    if (!ctx || !touched)
+        return arg_error("NULL argument");
+    pm::KArgs k;
+    base_args(ctx, k);
+    bool mixed = false;
+    pm_status s = conv_field(field, k.f, mixed);
+    if (!s)
+        s = conv_pool(in, "in", mixed, k.in);
+    if (!s)
+        s = conv_params(params, k);
+    if (!s)
+        s = check_range(ctx, in->nsub, 0, in->nsub);
+    if (s)
+        return s;
+    const int64_t nodes = k.f.sxy * (field->n[2] + 2 * field->halo);
+    if (!bitmap || nbits < nodes)
+        return arg_error("bitmap needs %lld bits", (long long)nodes);
+    hipStream_t st = (hipStream_t)stream;
+    k.sub_first = 0;
+    k.sub_count = in->nsub;
+    k.tile = ctx->shape.wg * ctx->shape.items;
+    const int64_t words = (nbits + 63) / 64;
+    PM_HIP(pm::launch_fill(bitmap, words, st), "fill launch");
+    PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn, st), "prep launch");
+    PM_HIP(pm::launch_touch(k, mixed, bitmap, st), "touch launch");
+    unsigned long long *cnt = (unsigned long long *)(ctx->ws.hdr + 8);
+    PM_HIP(hipMemsetAsync(cnt, 0, sizeof *cnt, st), "count clear");
+    PM_HIP(pm::launch_popcount(bitmap, words, cnt, st), "popcount launch");
+    unsigned long long h = 0;
+    PM_HIP(hipMemcpyAsync(&h, cnt, sizeof h, hipMemcpyDeviceToHost, st), "count read");
+    PM_HIP(hipStreamSynchronize(st), "stream sync");
+    *touched = (int64_t)h;
+    return PM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// pm_internal.h -- shared declarations of the HIP kernels and their host
+// launchers (library-internal; the public interface is include/pm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pm.h"
+
+namespace pm {
+
+// Look-back status word: two 31-bit bucket counts and a 2-bit state.
+constexpr int kLbWords = 14;              // 27 buckets, two per word
+constexpr uint64_t kLbA = 1ull << 62;     // tile aggregate published
+constexpr uint64_t kLbP = 2ull << 62;     // inclusive prefix published
+constexpr uint64_t kLbMask = (1ull << 62) - 1;
+constexpr uint64_t kM31 = 0x7fffffffull;
+constexpr uint32_t kMigrantSlot = 0xffffffffu;
+
+// Smallest tile any launch shape uses; sizes the look-back workspace.
+constexpr int kMinTile = 256;
+
+// Header words of the workspace.
+enum { kHdrFlags = 0, kHdrTicket = 1, kHdrTiles = 2, kHdrWords = 64 };
+
+struct DField {
+    const void *u[3];
+    int32_t n[3];
+    int32_t halo;
+    double r[3];     // n / L per axis
+    int64_t sx;      // stored row length (n0 + 2 halo)
+    int64_t sxy;     // stored plane size
+};
+
+struct DDecomp {
+    int32_t p[3];
+    int32_t nsub;
+    double b[3][PM_MAX_P + 1];
+    double L[3];
+    double predL[3]; // largest double below L
+};
+
+struct DPool {
+    const int64_t *base;
+    const int64_t *cap;
+    int64_t *count;
+    double *x[3];
+    void *v[3];
+    void *tau;
+    uint64_t *id;
+};
+
+struct DWS {
+    uint32_t *hdr;
+    int64_t *tile_start;   // [PM_MAX_NSUB + 1]
+    int64_t *stay;         // [nsub]
+    uint64_t *lb;          // [max_tiles * kLbWords]
+    uint32_t *slot;        // [pool_extent]
+    int64_t max_tiles;
+    int64_t pool_extent;
+    int64_t send_extent;
+};
+
+struct KArgs {
+    DField f;
+    DDecomp dc;
+    DPool in, out, send;
+    DWS ws;
+    double dt, half_dt, g[3];
+    float dtf, half_dtf, gf[3];
+    int32_t sub_first, sub_count;
+    int32_t tile;        // records per tile of this launch shape
+    int32_t cpt;         // append: workgroups per destination
+};
+
+// Prep kernel modes.
+enum {
+    kPrepTiles = 1,       // tile_start/ticket for the segment range
+    kPrepZeroLb = 2,      // clear the look-back words
+    kPrepZeroCounts = 4,  // clear send counts and stay counts of the range
+    kPrepCheckIn = 8,
+    kPrepCheckOut = 16,
+    kPrepCheckSend = 32,
+};
+
+struct Shape {
+    int wg;
+    int items;
+};
+
+// Launchers (pm_kernels.hip).  `mixed` selects float32 field/velocities.
+hipError_t launch_prep(const KArgs &a, int mode, hipStream_t st);
+hipError_t launch_step(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);
+hipError_t launch_advance(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);
+hipError_t launch_classify(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);
+hipError_t launch_compact(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);
+hipError_t launch_append(const KArgs &a, bool mixed, int grid, hipStream_t st);
+hipError_t launch_interp(const KArgs &a, bool mixed, int64_t n, const double *x,
+                         const double *y, const double *z, void *ux, void *uy,
+                         void *uz, hipStream_t st);
+hipError_t launch_touch(const KArgs &a, bool mixed, uint64_t *bitmap, hipStream_t st);
+hipError_t launch_popcount(const uint64_t *bitmap, int64_t words,
+                           unsigned long long *out, hipStream_t st);
+hipError_t launch_fill(uint64_t *p, int64_t words, hipStream_t st);
+
+// Workgroups per CU that fit for a launch shape of the fused kernel.
+int step_occupancy(Shape sh, bool mixed);
+bool shape_supported(Shape sh);
+
+}  // namespace pm

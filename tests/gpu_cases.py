@@ -1,0 +1,121 @@
+"""Shared set-up for the GPU tests: seeded workloads uploaded to the device,
+the matching oracle objects, and comparisons of pools."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2604_11008_amd import gen, pm
+
+# Q23-style tolerance: velocity-like values relative to max(|ref|_inf, u_rms=1),
+# positions relative to max(|x_ref|, cell width).
+TOL_F64 = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+class Case:
+    """A workload with host (oracle) and device (library) views."""
+
+    def __init__(self, name, npart=None, n=None, p=None, order="canonical", mode=None,
+                 face=0.1, edge=0.03, corner=0.02, dt_scale=1.0, slack=0.05, extra=1024):
+        say(f"[case] {name} np={npart} n={n} p={p} order={order} mode={mode}")
+        self.wl = gen.make_workload(name, np_override=npart, n_override=n, p_override=p,
+                                    order=order, slack=slack, extra=extra)
+        wl = self.wl
+        self.mode = mode or wl.mode
+        self.dt = wl.dt * dt_scale
+        self.g = wl.g
+        self.fh = wl.stored_field(np.float64)
+        self.ofield = oracle.Field(self.fh, wl.n, wl.halo, wl.L)
+        self.odc = oracle.Decomp(wl.p, wl.bounds)
+        U, _ = oracle.interp(self.ofield, wl.pool.x)
+        if self.mode == "mixed":
+            wl.pool.v = U.astype(np.float32)
+            wl.pool.tau = wl.pool.tau.astype(np.float32)
+        else:
+            wl.pool.v[:] = U
+        self.host = wl.pool
+        self.dev = torch.device("cuda:0")
+        fdev = [np.asarray(u, dtype=np.float32) for u in self.fh] if self.mode == "mixed" \
+            else self.fh
+        self.field = pm.DeviceField(fdev, wl.n, wl.halo, wl.L, device=self.dev)
+        self.dc = pm.Decomp(wl.p, wl.bounds)
+        self.sb, self.sc = gen.send_layout(wl.pool.count, face=face, edge=edge, corner=corner)
+        self.params = pm.Params(self.dt, self.g)
+        self.vdt = torch.float32 if self.mode == "mixed" else torch.float64
+
+    # device objects
+    def pin(self):
+        return pm.DevicePool.from_host(self.host, self.dev)
+
+    def pout(self, size):
+        return pm.DevicePool.empty(self.host.base, self.host.cap, vdtype=self.vdt,
+                                   device=self.dev, size=size)
+
+    def send(self):
+        return pm.DevicePool.empty(self.sb, self.sc, vdtype=self.vdt, device=self.dev)
+
+    def ctx(self, pin, send):
+        return pm.Context(pin.size, send.size, self.dc.nsub, device=self.dev)
+
+    # oracle step from the host state (promoted to float64)
+    def oracle_step(self, pool=None, dt=None):
+        pool = pool or self.host
+        out = gen.empty_pool(pool.base, pool.cap)
+        send = gen.empty_pool(self.sb, self.sc)
+        stay, flags = oracle.step(self.ofield, self.odc, self.dt if dt is None else dt,
+                                  self.g, pool, out, send)
+        return out, send, stay, flags
+
+
+def seg(pool, q):
+    b = int(pool.base[q])
+    c = int(min(pool.count[q], pool.cap[q]))
+    return slice(b, b + c)
+
+
+def compare_pools(got, ref, nseg, L, delta, tol=TOL_F64, exact=False, what="out"):
+    """Counts and ids exact; positions and velocities to tolerance (or bitwise)."""
+    np.testing.assert_array_equal(got.count[:nseg], ref.count[:nseg], err_msg=f"{what} counts")
+    vscale = max(1.0, float(np.abs(ref.v).max(initial=0.0)))
+    worst_x = worst_v = 0.0
+    for q in range(nseg):
+        s = seg(ref, q)
+        if s.stop == s.start:
+            continue
+        np.testing.assert_array_equal(got.id[s], ref.id[s], err_msg=f"{what} ids seg {q}")
+        gx, rx = got.x[:, s], ref.x[:, s]
+        gv, rv = got.v[:, s].astype(np.float64), ref.v[:, s].astype(np.float64)
+        if exact:
+            np.testing.assert_array_equal(gx, rx, err_msg=f"{what} x seg {q}")
+            np.testing.assert_array_equal(gv, rv, err_msg=f"{what} v seg {q}")
+            np.testing.assert_array_equal(got.tau[s], ref.tau[s])
+        else:
+            ex = np.abs(gx - rx) / np.maximum(np.abs(rx), delta)
+            ev = np.abs(gv - rv) / vscale
+            worst_x = max(worst_x, float(ex.max()))
+            worst_v = max(worst_v, float(ev.max()))
+            np.testing.assert_array_equal(got.tau[s].astype(np.float64),
+                                          ref.tau[s].astype(np.float64))
+    if not exact:
+        assert worst_x <= tol, f"{what}: position error {worst_x:.3e} > {tol:.1e}"
+        assert worst_v <= tol, f"{what}: velocity error {worst_v:.3e} > {tol:.1e}"
+    return worst_x, worst_v
+
+
+def assert_same_device_pools(a, b, nseg, what):
+    """Bitwise equality of two device pools' valid records."""
+    ha, hb = a.to_host(), b.to_host()
+    np.testing.assert_array_equal(ha.count[:nseg], hb.count[:nseg], err_msg=what)
+    for q in range(nseg):
+        s = seg(ha, q)
+        for name in ("x", "v", "tau", "id"):
+            np.testing.assert_array_equal(getattr(ha, name)[..., s], getattr(hb, name)[..., s],
+                                          err_msg=f"{what} {name} seg {q}")
