@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
     ap.add_argument("--tune", default=None, help="wg,items[,blocks_per_cu] or 'auto'")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
@@ -120,8 +121,7 @@ def main():
     pa.v.copy_(ctx.interp(field, pa.x))
     params = pm.Params(wl.dt, wl.g)
     if args.tune == "auto":
-        ctx.autotune(field, dc, pa, pb, send, params,
-                     cache_path=os.path.join(ROOT, "profiles", "tune_cache.txt"))
+        ctx.autotune(field, dc, pa, pb, send, params, cache_path=args.tune_cache)
     elif args.tune:
         t = [int(v) for v in args.tune.split(",")]
         ctx.set_tuning(*t)

@@ -160,13 +160,17 @@ typedef struct {
 
 typedef struct pm_ctx pm_ctx;
 
-/* Bytes of device workspace a context needs for pools of at most
- * pool_extent records (max over segments of base+cap) and nsub subdomains. */
-size_t pm_workspace_bytes(int64_t pool_extent, int32_t nsub);
+/* Bytes of device workspace a context needs for particle pools of at most
+ * pool_extent records (max over segments of base+cap), send buffers of at
+ * most send_extent records, and nsub subdomains.  It holds, besides small
+ * tables, one look-back word per tile, one slot per pool record for the
+ * plain path, and a staging area of send_extent leaver records (65 bytes
+ * each).  0 for invalid sizes. */
+size_t pm_workspace_bytes(int64_t pool_extent, int64_t send_extent, int32_t nsub);
 
 /* Create a context on the current device.  workspace: caller-owned device
- * memory of at least pm_workspace_bytes(pool_extent, nsub) bytes, 256-byte
- * aligned; send_extent: max over send segments of base+cap.  Synchronous. */
+ * memory of at least pm_workspace_bytes(pool_extent, send_extent, nsub)
+ * bytes, 256-byte aligned.  Synchronous. */
 pm_status pm_create(pm_ctx **ctx, void *workspace, size_t ws_bytes,
                     int64_t pool_extent, int64_t send_extent, int32_t nsub);
 pm_status pm_destroy(pm_ctx *ctx);

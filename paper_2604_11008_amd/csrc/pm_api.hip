@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -44,25 +45,37 @@ pm_status hip_error(hipError_t e, const char *what)
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct WsLayout {
-    size_t hdr, tile_start, stay, lb, slot, total;
-    int64_t max_tiles;
+    size_t hdr, tile_start, stay, migtot, stg_start, lb, slot, stg, total;
+    int64_t max_tiles, stg_extent;
 };
 
-WsLayout ws_layout(int64_t pool_extent, int32_t nsub)
+// Device workspace: header words, per-segment tables, one look-back word per
+// tile, the plain path's stayer slots, and the staging area of the leavers
+// (one record per send-buffer slot, 8-byte fields, plus a direction byte).
+WsLayout ws_layout(int64_t pool_extent, int64_t send_extent, int32_t nsub)
 {
     WsLayout L{};
     size_t o = 0;
+    const size_t ns = (size_t)std::max(nsub, 1);
     L.hdr = o;
     o += align256(pm::kHdrWords * sizeof(uint32_t));
     L.tile_start = o;
     o += align256((PM_MAX_NSUB + 1) * sizeof(int64_t));
     L.stay = o;
-    o += align256((size_t)std::max(nsub, 1) * sizeof(int64_t));
+    o += align256(ns * sizeof(int64_t));
+    L.migtot = o;
+    o += align256(ns * sizeof(int64_t));
+    L.stg_start = o;
+    o += align256((PM_MAX_NSUB + 1) * sizeof(int64_t));
     L.max_tiles = pool_extent / pm::kMinTile + nsub + 2;
     L.lb = o;
-    o += align256((size_t)L.max_tiles * pm::kLbWords * sizeof(uint64_t));
+    o += align256((size_t)L.max_tiles * sizeof(uint64_t));
     L.slot = o;
     o += align256((size_t)std::max<int64_t>(pool_extent, 1) * sizeof(uint32_t));
+    // every segment's staging area is rounded up to a multiple of 16 records
+    L.stg_extent = send_extent + 16 * (int64_t)ns + 16;
+    L.stg = o;
+    o += 8 * align256((size_t)L.stg_extent * 8) + align256((size_t)L.stg_extent);
     L.total = o;
     return L;
 }
@@ -231,9 +244,9 @@ pm_status check_range(pm_ctx *ctx, int32_t nsub, int32_t first, int32_t count)
     return PM_OK;
 }
 
-int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed)
+int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed, bool halo)
 {
-    const int occ = pm::step_occupancy(sh, mixed);
+    const int occ = pm::step_occupancy(sh, mixed, halo);
     const int per = ctx->blocks_per_cu > 0 ? std::min(ctx->blocks_per_cu, occ) : occ;
     return std::max(1, ctx->cus * per);
 }
@@ -246,20 +259,20 @@ pm_status queue_step(pm_ctx *ctx, pm::KArgs &k, bool mixed, hipStream_t st, bool
     k.tile = ctx->shape.wg * ctx->shape.items;
     k.cpt = append_cpt(k.sub_count);
     PM_HIP(pm::launch_prep(k,
-                           pm::kPrepTiles | pm::kPrepZeroLb | pm::kPrepZeroCounts |
-                               pm::kPrepCheckIn | pm::kPrepCheckOut | pm::kPrepCheckSend,
+                           pm::kPrepTiles | pm::kPrepStaging | pm::kPrepZeroLb |
+                               pm::kPrepZeroCounts | pm::kPrepCheckIn | pm::kPrepCheckOut |
+                               pm::kPrepCheckSend,
                            st),
            "prep launch");
     if (timed)
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount], st), "event record");
-    PM_HIP(pm::launch_step(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed), st),
+    PM_HIP(pm::launch_step(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed, k.f.halo != 0), st),
            "fused step launch");
     if (timed) {
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount + 1], st), "event record");
         ctx->tcount++;
     }
-    const int grid = std::min(4096, k.sub_count * k.cpt);
-    PM_HIP(pm::launch_append(k, mixed, std::max(1, grid), st), "append launch");
+    PM_HIP(pm::launch_route(k, mixed, true, st), "route launch");
     return PM_OK;
 }
 
@@ -279,11 +292,11 @@ extern "C" {
 
 const char *pm_last_error(void) { return g_err.c_str(); }
 
-size_t pm_workspace_bytes(int64_t pool_extent, int32_t nsub)
+size_t pm_workspace_bytes(int64_t pool_extent, int64_t send_extent, int32_t nsub)
 {
-    if (pool_extent < 0 || nsub < 1)
+    if (pool_extent < 0 || send_extent < 0 || nsub < 1)
         return 0;
-    return ws_layout(pool_extent, nsub).total;
+    return ws_layout(pool_extent, send_extent, nsub).total;
 }
 
 pm_status pm_create(pm_ctx **out, void *workspace, size_t ws_bytes, int64_t pool_extent,
@@ -296,30 +309,50 @@ pm_status pm_create(pm_ctx **out, void *workspace, size_t ws_bytes, int64_t pool
         return arg_error("nsub = %d not in 1..%d", nsub, PM_MAX_NSUB);
     if (pool_extent < 0 || pool_extent > ((int64_t)1 << 34) || send_extent < 0)
         return arg_error("pool or send extent out of range");
-    const WsLayout L = ws_layout(pool_extent, nsub);
+    const WsLayout L = ws_layout(pool_extent, send_extent, nsub);
     if (!workspace || ws_bytes < L.total)
         return arg_error("workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
                          L.total);
     if (((uintptr_t)workspace & 255u) != 0)
         return arg_error("workspace must be 256-byte aligned");
     pm_ctx *ctx = new pm_ctx();
-    PM_HIP(hipGetDevice(&ctx->device), "hipGetDevice");
-    PM_HIP(hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device),
-           "device attribute");
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    if (e != hipSuccess) {
+        delete ctx;
+        return hip_error(e, "device query");
+    }
     char *w = (char *)workspace;
     ctx->ws.hdr = (uint32_t *)(w + L.hdr);
     ctx->ws.tile_start = (int64_t *)(w + L.tile_start);
     ctx->ws.stay = (int64_t *)(w + L.stay);
+    ctx->ws.migtot = (int64_t *)(w + L.migtot);
+    ctx->ws.stg_start = (int64_t *)(w + L.stg_start);
     ctx->ws.lb = (uint64_t *)(w + L.lb);
     ctx->ws.slot = (uint32_t *)(w + L.slot);
+    const size_t fs = align256((size_t)L.stg_extent * 8);
+    char *g = w + L.stg;
+    for (int c = 0; c < 3; ++c) {
+        ctx->ws.stg_x[c] = (double *)(g + c * fs);
+        ctx->ws.stg_v[c] = (double *)(g + (3 + c) * fs);
+    }
+    ctx->ws.stg_tau = (double *)(g + 6 * fs);
+    ctx->ws.stg_id = (uint64_t *)(g + 7 * fs);
+    ctx->ws.stg_d = (uint8_t *)(g + 8 * fs);
     ctx->ws.max_tiles = L.max_tiles;
     ctx->ws.pool_extent = pool_extent;
     ctx->ws.send_extent = send_extent;
+    ctx->ws.stg_extent = L.stg_extent;
     ctx->nsub_max = nsub;
-    // start from a clean header, tile table and look-back state
-    PM_HIP(hipMemset(workspace, 0, L.lb + (size_t)L.max_tiles * pm::kLbWords * sizeof(uint64_t)),
-           "workspace clear");
-    PM_HIP(hipDeviceSynchronize(), "workspace clear");
+    // start from a clean header, tables and look-back state
+    e = hipMemset(workspace, 0, L.slot);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete ctx;
+        return hip_error(e, "workspace clear");
+    }
     *out = ctx;
     return PM_OK;
 }
@@ -386,7 +419,7 @@ pm_status pm_interp_advance(pm_ctx *ctx, const pm_field *field, pm_particles *in
     k.sub_count = sub_count;
     k.tile = ctx->shape.wg * ctx->shape.items;
     PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn, st), "prep launch");
-    PM_HIP(pm::launch_advance(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed), st),
+    PM_HIP(pm::launch_advance(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed, k.f.halo != 0), st),
            "advance launch");
     return PM_OK;
 }
@@ -422,12 +455,13 @@ pm_status pm_classify_scan_pack(pm_ctx *ctx, const pm_decomp *decomp, const pm_p
     k.sub_count = sub_count;
     k.tile = ctx->shape.wg * ctx->shape.items;
     PM_HIP(pm::launch_prep(k,
-                           pm::kPrepTiles | pm::kPrepZeroLb | pm::kPrepZeroCounts |
-                               pm::kPrepCheckIn | pm::kPrepCheckSend,
+                           pm::kPrepTiles | pm::kPrepStaging | pm::kPrepZeroLb |
+                               pm::kPrepZeroCounts | pm::kPrepCheckIn | pm::kPrepCheckSend,
                            st),
            "prep launch");
-    PM_HIP(pm::launch_classify(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed), st),
+    PM_HIP(pm::launch_classify(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed, k.f.halo != 0), st),
            "classify launch");
+    PM_HIP(pm::launch_route(k, mixed, false, st), "route launch");
     return PM_OK;
 }
 
@@ -467,7 +501,7 @@ pm_status pm_compact_append(pm_ctx *ctx, const pm_decomp *decomp, const pm_parti
                                   pm::kPrepCheckSend,
                            st),
            "prep launch");
-    PM_HIP(pm::launch_compact(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed), st),
+    PM_HIP(pm::launch_compact(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed, k.f.halo != 0), st),
            "compact launch");
     const int grid = std::min(4096, sub_count * k.cpt);
     PM_HIP(pm::launch_append(k, mixed, std::max(1, grid), st), "append launch");
@@ -694,7 +728,7 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
     int best_bpc = ctx->blocks_per_cu;
     for (const auto &sh : shapes) {
         for (int bpc : bpcs) {
-            if (bpc > pm::step_occupancy(sh, mixed))
+            if (bpc > pm::step_occupancy(sh, mixed, k.f.halo != 0))
                 continue;
             ctx->shape = sh;
             ctx->blocks_per_cu = bpc;
@@ -713,6 +747,9 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
             float ms = 0.f;
             PM_HIP(hipEventElapsedTime(&ms, e0, e1), "elapsed");
             ms /= reps;
+            if (getenv("PM_TUNE_VERBOSE"))
+                fprintf(stderr, "pm_autotune: wg=%d items=%d bpc=%d %.4f ms/step\n", sh.wg,
+                        sh.items, bpc, ms);
             if (ms < best) {
                 best = ms;
                 best_sh = sh;

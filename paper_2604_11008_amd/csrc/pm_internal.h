@@ -9,8 +9,8 @@
 
 namespace pm {
 
-// Look-back status word: two 31-bit bucket counts and a 2-bit state.
-constexpr int kLbWords = 14;              // 27 buckets, two per word
+// Look-back status word of a tile: the tile's count of stayers (bits 0-30)
+// and of leavers (bits 31-61), and a 2-bit state (bits 62-63).
 constexpr uint64_t kLbA = 1ull << 62;     // tile aggregate published
 constexpr uint64_t kLbP = 2ull << 62;     // inclusive prefix published
 constexpr uint64_t kLbMask = (1ull << 62) - 1;
@@ -52,13 +52,22 @@ struct DPool {
 
 struct DWS {
     uint32_t *hdr;
-    int64_t *tile_start;   // [PM_MAX_NSUB + 1]
-    int64_t *stay;         // [nsub]
-    uint64_t *lb;          // [max_tiles * kLbWords]
-    uint32_t *slot;        // [pool_extent]
+    int64_t *tile_start;   // [PM_MAX_NSUB + 1] first ticket of each segment of the range
+    int64_t *stay;         // [nsub] stayers per segment
+    int64_t *migtot;       // [nsub] leavers per segment
+    int64_t *stg_start;    // [PM_MAX_NSUB + 1] staging offset of each segment of the range
+    uint64_t *lb;          // [max_tiles] look-back status words
+    uint32_t *slot;        // [pool_extent] stayer slots (plain path)
+    // staging of the leavers, in scan order per segment: [stg_extent]
+    double *stg_x[3];
+    double *stg_v[3];      // read as float in the mixed mode
+    double *stg_tau;
+    uint64_t *stg_id;
+    uint8_t *stg_d;
     int64_t max_tiles;
     int64_t pool_extent;
     int64_t send_extent;
+    int64_t stg_extent;
 };
 
 struct KArgs {
@@ -81,6 +90,7 @@ enum {
     kPrepCheckIn = 8,
     kPrepCheckOut = 16,
     kPrepCheckSend = 32,
+    kPrepStaging = 64,    // staging offsets of the range from the send capacities
 };
 
 struct Shape {
@@ -95,6 +105,7 @@ hipError_t launch_advance(const KArgs &a, Shape sh, bool mixed, int grid, hipStr
 hipError_t launch_classify(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);
 hipError_t launch_compact(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);
 hipError_t launch_append(const KArgs &a, bool mixed, int grid, hipStream_t st);
+hipError_t launch_route(const KArgs &a, bool mixed, bool append, hipStream_t st);
 hipError_t launch_interp(const KArgs &a, bool mixed, int64_t n, const double *x,
                          const double *y, const double *z, void *ux, void *uy,
                          void *uz, hipStream_t st);
@@ -104,7 +115,7 @@ hipError_t launch_popcount(const uint64_t *bitmap, int64_t words,
 hipError_t launch_fill(uint64_t *p, int64_t words, hipStream_t st);
 
 // Workgroups per CU that fit for a launch shape of the fused kernel.
-int step_occupancy(Shape sh, bool mixed);
+int step_occupancy(Shape sh, bool mixed, bool halo);
 bool shape_supported(Shape sh);
 
 }  // namespace pm

@@ -130,34 +130,62 @@ __device__ __forceinline__ int next_corner(const DField &f, int a, int c0)
     return c0 + 1 == f.n[a] ? 0 : c0 + 1;
 }
 
-// U(X) with the field in FT; the weights are the float64 fractions rounded
-// to FT.  Evaluated as x-, then y-, then z-lerps.
+// The 2x2x2 stencil of one position: stored corner indices along each axis
+// and the cell fractions (computed in float64, rounded to FT).
+template <typename FT, bool HALO>
+__device__ __forceinline__ void stencil_index(const DField &f, const double X[3], int c0[3],
+                                              FT fr[3], uint32_t &fl)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        fr[a] = (FT)axis_corner<HALO>(f, a, X[a], c0[a], fl);
+}
+
+// The 24 node values of a stencil: v[c][2*r + x] for component c, row r
+// (y and z corner: 00, 10, 01, 11) and x corner x.
+template <typename FT, bool HALO>
+__device__ __forceinline__ void stencil_load(const DField &f, const int c0[3], FT v[3][8])
+{
+    const int cx1 = next_corner<HALO>(f, 0, c0[0]);
+    const int cy1 = next_corner<HALO>(f, 1, c0[1]);
+    const int cz1 = next_corner<HALO>(f, 2, c0[2]);
+    const int64_t r[4] = {f.sx * (int64_t)c0[1] + f.sxy * (int64_t)c0[2],
+                          f.sx * (int64_t)cy1 + f.sxy * (int64_t)c0[2],
+                          f.sx * (int64_t)c0[1] + f.sxy * (int64_t)cz1,
+                          f.sx * (int64_t)cy1 + f.sxy * (int64_t)cz1};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const FT *u = (const FT *)f.u[c];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[c][2 * k] = u[r[k] + c0[0]];
+            v[c][2 * k + 1] = u[r[k] + cx1];
+        }
+    }
+}
+
+// U from a loaded stencil: x-, then y-, then z-lerps.
+template <typename FT>
+__device__ __forceinline__ void stencil_eval(const FT v[3][8], const FT fr[3], FT U[3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const FT l00 = lerp(v[c][0], v[c][1], fr[0]), l10 = lerp(v[c][2], v[c][3], fr[0]);
+        const FT l01 = lerp(v[c][4], v[c][5], fr[0]), l11 = lerp(v[c][6], v[c][7], fr[0]);
+        U[c] = lerp(lerp(l00, l10, fr[1]), lerp(l01, l11, fr[1]), fr[2]);
+    }
+}
+
+// U(X) by trilinear interpolation (Sect. 2.2).
 template <typename FT, bool HALO>
 __device__ __forceinline__ void interp(const DField &f, const double X[3], FT U[3],
                                        uint32_t &fl)
 {
-    int cx0, cy0, cz0;
-    const FT fx = (FT)axis_corner<HALO>(f, 0, X[0], cx0, fl);
-    const FT fy = (FT)axis_corner<HALO>(f, 1, X[1], cy0, fl);
-    const FT fz = (FT)axis_corner<HALO>(f, 2, X[2], cz0, fl);
-    const int cx1 = next_corner<HALO>(f, 0, cx0);
-    const int cy1 = next_corner<HALO>(f, 1, cy0);
-    const int cz1 = next_corner<HALO>(f, 2, cz0);
-    const int64_t r00 = f.sx * (int64_t)cy0 + f.sxy * (int64_t)cz0;
-    const int64_t r10 = f.sx * (int64_t)cy1 + f.sxy * (int64_t)cz0;
-    const int64_t r01 = f.sx * (int64_t)cy0 + f.sxy * (int64_t)cz1;
-    const int64_t r11 = f.sx * (int64_t)cy1 + f.sxy * (int64_t)cz1;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const FT *u = (const FT *)f.u[c];
-        const FT a00 = u[r00 + cx0], b00 = u[r00 + cx1];
-        const FT a10 = u[r10 + cx0], b10 = u[r10 + cx1];
-        const FT a01 = u[r01 + cx0], b01 = u[r01 + cx1];
-        const FT a11 = u[r11 + cx0], b11 = u[r11 + cx1];
-        const FT l00 = lerp(a00, b00, fx), l10 = lerp(a10, b10, fx);
-        const FT l01 = lerp(a01, b01, fx), l11 = lerp(a11, b11, fx);
-        U[c] = lerp(lerp(l00, l10, fy), lerp(l01, l11, fy), fz);
-    }
+    int c0[3];
+    FT fr[3], v[3][8];
+    stencil_index<FT, HALO>(f, X, c0, fr, fl);
+    stencil_load<FT, HALO>(f, c0, v);
+    stencil_eval<FT>(v, fr, U);
 }
 
 // ---------------------------------------------------------------------------
@@ -175,27 +203,56 @@ template <typename FT> __device__ __forceinline__ FT kg(const KArgs &a, int c);
 template <> __device__ __forceinline__ double kg<double>(const KArgs &a, int c) { return a.g[c]; }
 template <> __device__ __forceinline__ float kg<float>(const KArgs &a, int c) { return a.gf[c]; }
 
-template <typename FT, bool HALO>
-__device__ __forceinline__ void advance(const KArgs &a, double X[3], FT V[3], FT tau,
-                                        uint32_t &fl)
+// Heun step of N particles, phase by phase: stage-1 indices, stage-1 loads,
+// stage-1 updates and stage-2 indices, stage-2 loads of the stencils that
+// changed cell, final update.  Each particle's arithmetic does not depend on
+// N.  The kernels use N = 1 per record: batching several records this way
+// needs 24 stencil values per record in registers at once, and the lost
+// occupancy costs more than the overlap gains.
+template <typename FT, bool HALO, int N>
+__device__ __forceinline__ void advance_items(const KArgs &a, double (*X)[3], FT (*V)[3],
+                                              const FT *tau, uint32_t &fl)
 {
-    const FT it = (FT)1 / tau;
     const FT dt = kdt<FT>(a), hdt = khdt<FT>(a);
-    FT U1[3], A1[3], Vs[3], U2[3];
-    double Xs[3];
-    interp<FT, HALO>(a.f, X, U1, fl);
+    int c1[N][3], c2[N][3];
+    FT fr[N][3], S[N][3][8], A1[N][3], Vs[N][3], it[N];
+    bool moved[N];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        A1[c] = fma(U1[c] - V[c], it, kg<FT>(a, c));
-        Xs[c] = fma(a.dt, (double)V[c], X[c]);
-        Vs[c] = fma(dt, A1[c], V[c]);
+    for (int k = 0; k < N; ++k)
+        stencil_index<FT, HALO>(a.f, X[k], c1[k], fr[k], fl);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        stencil_load<FT, HALO>(a.f, c1[k], S[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        FT U1[3];
+        double Xs[3];
+        stencil_eval<FT>(S[k], fr[k], U1);
+        it[k] = (FT)1 / tau[k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            A1[k][c] = fma(U1[c] - V[k][c], it[k], kg<FT>(a, c));
+            Xs[c] = fma(a.dt, (double)V[k][c], X[k][c]);
+            Vs[k][c] = fma(dt, A1[k][c], V[k][c]);
+        }
+        stencil_index<FT, HALO>(a.f, Xs, c2[k], fr[k], fl);
+        moved[k] = c2[k][0] != c1[k][0] || c2[k][1] != c1[k][1] || c2[k][2] != c1[k][2];
     }
-    interp<FT, HALO>(a.f, Xs, U2, fl);
+    // stage 2 mostly falls in the same cell, whose node values are loaded
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const FT A2 = fma(U2[c] - Vs[c], it, kg<FT>(a, c));
-        X[c] = fma(a.half_dt, (double)V[c] + (double)Vs[c], X[c]);
-        V[c] = fma(hdt, A1[c] + A2, V[c]);
+    for (int k = 0; k < N; ++k)
+        if (moved[k])
+            stencil_load<FT, HALO>(a.f, c2[k], S[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        FT U2[3];
+        stencil_eval<FT>(S[k], fr[k], U2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const FT A2 = fma(U2[c] - Vs[k][c], it[k], kg<FT>(a, c));
+            X[k][c] = fma(a.half_dt, (double)V[k][c] + (double)Vs[k][c], X[k][c]);
+            V[k][c] = fma(hdt, A1[k][c] + A2, V[k][c]);
+        }
     }
 }
 
@@ -258,16 +315,18 @@ __device__ __forceinline__ int classify(const DDecomp &dc, const int own[3],
 
 struct TileHead {
     int64_t q, qhead, first;
-    int32_t s, nitems, last;
+    int32_t s, sl, nitems, last;
 };
 
+// The cross-tile scan carries two counts per tile, stayers and leavers
+// (the paper's send/stay mask); leavers are split by direction afterwards.
 template <int WG, int ITEMS>
 struct TileLds {
     static constexpr int E = ITEMS * (WG / 64);
-    uint32_t cnt[27][E];     // per (stripe, wave) counts, then their tile prefix
-    uint32_t agg[27];        // tile totals
-    uint32_t base[27];       // tile's offset within its segment
-    uint32_t present;        // buckets that occur in the tile
+    uint32_t cnt[2][E];      // per (stripe, wave) counts, then their tile prefix
+    uint32_t agg[2];         // tile totals
+    uint32_t base[2];        // the tile's offset within its segment
+    uint32_t dcnt[27];       // leavers per direction
     TileHead h;
 };
 
@@ -291,72 +350,75 @@ __device__ __forceinline__ void locate(const KArgs &a, int tile, int64_t q, Tile
     h.q = q;
     h.qhead = qh;
     h.s = s;
+    h.sl = lo;
     h.first = a.in.base[s] + j * tile;
     h.nitems = (int32_t)(left < tile ? left : tile);
     h.last = (q == ts[lo + 1] - 1);
 }
 
-// Ranks of the tile's valid records within their bucket: afterwards
-// slot = L.base[b] + L.cnt[b][k*NW + w] + rank[k] is the record's slot in
-// its segment's bucket b.  d == 0xff marks an absent record.
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int lo = __shfl_xor((int)(uint32_t)v, off, 64);
+        const int hi = __shfl_xor((int)(uint32_t)(v >> 32), off, 64);
+        v += ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    }
+    return v;
+}
+
+// Ranks of the tile's valid records: a stayer's among the stayers, a
+// leaver's among the leavers; afterwards the record's slot in its segment is
+// L.base[c] + L.cnt[c][k*NW + w] + rank[k] (c = 0 stay, 1 leave).
+// d == 0xff marks an absent record.
 template <int WG, int ITEMS>
-__device__ __forceinline__ void tile_ranks(const KArgs &a, TileLds<WG, ITEMS> &L,
-                                           const int (&d)[ITEMS], uint32_t (&rank)[ITEMS])
+__device__ __forceinline__ void tile_ranks(TileLds<WG, ITEMS> &L, const int (&d)[ITEMS],
+                                           uint32_t (&rank)[ITEMS])
 {
     constexpr int NW = WG / 64;
     constexpr int E = TileLds<WG, ITEMS>::E;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
 
-    for (int e = tid; e < 27 * E; e += WG)
+    for (int e = tid; e < 2 * E; e += WG)
         (&L.cnt[0][0])[e] = 0u;
-    if (tid == 0)
-        L.present = 1u << PM_STAY;
+    if (tid < 27)
+        L.dcnt[tid] = 0u;
     __syncthreads();
 
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const uint64_t stay = __ballot(d[k] == PM_STAY);
-        uint64_t mig = __ballot(d[k] < 27 && d[k] != PM_STAY);
-        rank[k] = (uint32_t)__popcll(stay & lt);
-        if (lane == 0)
-            L.cnt[PM_STAY][k * NW + w] = (uint32_t)__popcll(stay);
-        uint32_t seen = 0;
-        while (mig) {
-            const int src = __ffsll((unsigned long long)mig) - 1;
-            const int dd = __shfl(d[k], src, 64);
-            const uint64_t same = __ballot(d[k] == dd);
-            if (d[k] == dd)
-                rank[k] = (uint32_t)__popcll(same & lt);
-            if (lane == 0)
-                L.cnt[dd][k * NW + w] = (uint32_t)__popcll(same);
-            seen |= 1u << dd;
-            mig &= ~same;
+        const bool st = d[k] == PM_STAY;
+        const bool mg = d[k] < 27 && !st;
+        const uint64_t stay = __ballot(st);
+        const uint64_t mig = __ballot(mg);
+        rank[k] = (uint32_t)__popcll((st ? stay : mig) & lt);
+        if (lane == 0) {
+            L.cnt[0][k * NW + w] = (uint32_t)__popcll(stay);
+            L.cnt[1][k * NW + w] = (uint32_t)__popcll(mig);
         }
-        if (lane == 0 && seen)
-            atomicOr(&L.present, seen);
+        if (mig && mg)
+            atomicAdd(&L.dcnt[d[k]], 1u);
     }
     __syncthreads();
 
-    if (tid < 27) {
+    if (tid < 2) {
         uint32_t run = 0;
-        if ((L.present >> tid) & 1u) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const uint32_t c = L.cnt[tid][e];
-                L.cnt[tid][e] = run;
-                run += c;
-            }
+        for (int e = 0; e < E; ++e) {
+            const uint32_t c = L.cnt[tid][e];
+            L.cnt[tid][e] = run;
+            run += c;
         }
         L.agg[tid] = run;
     }
     __syncthreads();
 }
 
-// Decoupled look-back over the tiles of one segment (wave 0 only): every
-// status word carries buckets 2w and 2w+1; each word's chain is walked on
-// its own until a predecessor with an inclusive prefix, or the segment's
-// first tile, is reached.  Writes L.base.
+// Decoupled look-back over the tiles of one segment, by wave 0: every lane
+// reads one predecessor's status word, so each round trip covers 64 tiles;
+// the walk ends at the nearest predecessor with an inclusive prefix, or at
+// the segment's first tile.  Writes L.base.
 template <int WG, int ITEMS>
 __device__ __forceinline__ void lookback(const KArgs &a, TileLds<WG, ITEMS> &L)
 {
@@ -364,68 +426,56 @@ __device__ __forceinline__ void lookback(const KArgs &a, TileLds<WG, ITEMS> &L)
     if (lane >= 64)
         return;
     const TileHead &h = L.h;
-    uint64_t agg = 0;
-    if (lane < kLbWords) {
-        const uint64_t lo = L.agg[2 * lane];
-        const uint64_t hi = (2 * lane + 1 < 27) ? L.agg[2 * lane + 1] : 0ull;
-        agg = lo | (hi << 31);
-    }
-    uint64_t *mine = a.ws.lb + h.q * kLbWords;
+    const uint64_t agg = (uint64_t)L.agg[0] | ((uint64_t)L.agg[1] << 31);
+    uint64_t *lb = a.ws.lb;
     uint64_t excl = 0;
     if (h.q == h.qhead) {
-        if (lane < kLbWords)
-            lb_store(mine + lane, kLbP | agg);
+        if (lane == 0)
+            lb_store(lb + h.q, kLbP | agg);
     } else {
-        if (lane < kLbWords)
-            lb_store(mine + lane, kLbA | agg);
-        bool done = lane >= kLbWords;
-        const int pp = lane / kLbWords, ww = lane % kLbWords;
+        if (lane == 0)
+            lb_store(lb + h.q, kLbA | agg);
         int64_t pb = h.q - 1;
         for (;;) {
-            const int64_t t = pb - pp;
+            const int64_t t = pb - lane;
             uint64_t v = kLbP;  // before the segment's first tile: a zero prefix
-            if (lane < 4 * kLbWords && t >= h.qhead) {
-                const uint64_t *wp = a.ws.lb + t * kLbWords + ww;
-                v = lb_load(wp);
+            if (t >= h.qhead) {
+                v = lb_load(lb + t);
                 while ((v >> 62) == 0ull) {
                     __builtin_amdgcn_s_sleep(1);
-                    v = lb_load(wp);
+                    v = lb_load(lb + t);
                 }
             }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint64_t vk = shfl64(v, (k * kLbWords + lane) & 63);
-                if (!done) {
-                    excl += vk & kLbMask;
-                    if ((vk >> 62) == 2ull)
-                        done = true;
-                }
-            }
-            if (__ballot(!done) == 0ull)
+            const uint64_t pmask = __ballot((v >> 62) == 2ull);
+            if (pmask) {
+                const int k = __ffsll((unsigned long long)pmask) - 1;
+                excl += wave_sum64(lane <= k ? (v & kLbMask) : 0ull);
                 break;
-            pb -= 4;
+            }
+            excl += wave_sum64(v & kLbMask);
+            pb -= 64;
         }
-        if (lane < kLbWords)
-            lb_store(mine + lane, kLbP | (excl + agg));
+        if (lane == 0)
+            lb_store(lb + h.q, kLbP | (excl + agg));
     }
-    if (lane < kLbWords) {
-        L.base[2 * lane] = (uint32_t)(excl & kM31);
-        if (2 * lane + 1 < 27)
-            L.base[2 * lane + 1] = (uint32_t)((excl >> 31) & kM31);
+    if (lane == 0) {
+        L.base[0] = (uint32_t)(excl & kM31);
+        L.base[1] = (uint32_t)((excl >> 31) & kM31);
     }
 }
 
-// The segment's last tile publishes the segment totals.
+// After the scatter: per-direction leaver counts of the tile into the
+// segment's send counts, and the segment totals from its last tile.
 template <int WG, int ITEMS>
-__device__ __forceinline__ void publish_totals(const KArgs &a, const TileLds<WG, ITEMS> &L)
+__device__ __forceinline__ void publish_counts(const KArgs &a, const TileLds<WG, ITEMS> &L)
 {
     const int tid = threadIdx.x;
-    if (L.h.last && tid < 27) {
-        const int64_t tot = (int64_t)L.base[tid] + (int64_t)L.agg[tid];
-        if (tid == PM_STAY)
-            a.ws.stay[L.h.s] = tot;
-        else
-            a.send.count[(int64_t)L.h.s * 27 + tid] = tot;
+    if (tid < 27 && tid != PM_STAY && L.dcnt[tid])
+        atomicAdd((unsigned long long *)&a.send.count[(int64_t)L.h.s * 27 + tid],
+                  (unsigned long long)L.dcnt[tid]);
+    if (L.h.last && tid == 0) {
+        a.ws.stay[L.h.s] = (int64_t)L.base[0] + L.agg[0];
+        a.ws.migtot[L.h.s] = (int64_t)L.base[1] + L.agg[1];
     }
 }
 
@@ -442,70 +492,134 @@ __device__ __forceinline__ void put_record(const DPool &P, int64_t at, const dou
     P.id[at] = id;
 }
 
+template <typename FT>
+__device__ __forceinline__ void put_staged(const DWS &ws, int64_t at, const double X[3],
+                                           const FT V[3], FT tau, uint64_t id, int d)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        ws.stg_x[c][at] = X[c];
+        ((FT *)ws.stg_v[c])[at] = V[c];
+    }
+    ((FT *)ws.stg_tau)[at] = tau;
+    ws.stg_id[at] = id;
+    ws.stg_d[at] = (uint8_t)d;
+}
+
+__device__ __forceinline__ int neighbour(const DDecomp &dc, int s, int d, int sign)
+{
+    int o[3];
+    owner_xyz(dc, s, o);
+    int r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int P = dc.p[c];
+        r[c] = ((o[c] + sign * dir_o(d, c)) % P + P) % P;
+    }
+    return r[0] + dc.p[0] * (r[1] + dc.p[1] * r[2]);
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
 
-// Per-call set-up: the tile table of the segment range (one workgroup),
-// clearing of the look-back words and counts, and layout checks.
-__global__ __launch_bounds__(1024) void k_prep(const KArgs a, int mode)
+// Exclusive scan over the 256 threads of a workgroup (wave shuffles, then
+// the four wave totals); returns the exclusive prefix, *total the sum.
+__device__ __forceinline__ int64_t block_scan256(int64_t x, int64_t *wsum, int64_t *total)
 {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int64_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int lo = __shfl_up((int)(uint32_t)incl, off, 64);
+        const int hi = __shfl_up((int)(uint32_t)((uint64_t)incl >> 32), off, 64);
+        const int64_t t = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+        if (lane >= off)
+            incl += t;
+    }
+    if (lane == 63)
+        wsum[w] = incl;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        before += k < w ? wsum[k] : 0;
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - x;
+}
+
+// Per-call set-up: tile table and staging offsets of the segment range
+// (workgroup 0), clearing of the look-back words and counts, layout checks.
+__global__ __launch_bounds__(256) void k_prep(const KArgs a, int mode)
+{
+    constexpr int PER = (PM_MAX_NSUB + 255) / 256;
+    __shared__ int64_t wsum[4];
     uint32_t *hdr = a.ws.hdr;
     const int tid = threadIdx.x;
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + tid;
     const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
     uint32_t bad = 0;
 
-    if ((mode & kPrepTiles) && blockIdx.x == 0) {
-        // exclusive scan of ceil(count/tile) over the range, 4 per thread
-        __shared__ int64_t part[1024];
-        int64_t v[4];
-        int64_t sum = 0;
+    if ((mode & (kPrepTiles | kPrepStaging)) && blockIdx.x == 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+            if (!(mode & (pass == 0 ? kPrepTiles : kPrepStaging)))
+                continue;
+            int64_t v[PER];
+            int64_t sum = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int i = tid * 4 + k;
-            int64_t c = 0;
-            if (i < a.sub_count) {
-                c = a.in.count[a.sub_first + i];
-                c = c > 0 ? (c + a.tile - 1) / a.tile : 0;
+            for (int k = 0; k < PER; ++k) {
+                const int i = tid * PER + k;
+                int64_t c = 0;
+                if (i < a.sub_count) {
+                    const int64_t s = a.sub_first + i;
+                    if (pass == 0) {
+                        c = a.in.count[s];
+                        c = c > 0 ? (c + a.tile - 1) / a.tile : 0;
+                    } else {
+                        for (int d = 0; d < 27; ++d) {
+                            const int64_t cp = a.send.cap[s * 27 + d];
+                            c += (d != PM_STAY && cp > 0) ? cp : 0;
+                        }
+                        c = (c + 15) & ~(int64_t)15;  // 16-aligned staging areas
+                    }
+                }
+                v[k] = c;
+                sum += c;
             }
-            v[k] = c;
-            sum += c;
-        }
-        part[tid] = sum;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int64_t x = tid >= off ? part[tid - off] : 0;
-            __syncthreads();
-            part[tid] += x;
-            __syncthreads();
-        }
-        int64_t run = part[tid] - sum;
+            int64_t total;
+            int64_t run = block_scan256(sum, wsum, &total);
+            int64_t *dst = pass == 0 ? a.ws.tile_start : a.ws.stg_start;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int i = tid * 4 + k;
-            if (i <= a.sub_count)
-                a.ws.tile_start[i] = run;
-            run += v[k];
-        }
-        if (tid == 1023) {
-            const int64_t total = part[1023];
-            a.ws.tile_start[a.sub_count] = total;
-            if (total > a.ws.max_tiles) {
-                bad |= PM_F_LAYOUT;
-                hdr[kHdrTiles] = 0u;
-            } else {
-                hdr[kHdrTiles] = (uint32_t)total;
+            for (int k = 0; k < PER; ++k) {
+                const int i = tid * PER + k;
+                if (i < a.sub_count)
+                    dst[i] = run;
+                run += v[k];
             }
-            hdr[kHdrTicket] = 0u;
+            if (tid == 0) {
+                dst[a.sub_count] = total;
+                if (pass == 0) {
+                    if (total > a.ws.max_tiles) {
+                        bad |= PM_F_LAYOUT;
+                        hdr[kHdrTiles] = 0u;
+                    } else {
+                        hdr[kHdrTiles] = (uint32_t)total;
+                    }
+                    hdr[kHdrTicket] = 0u;
+                } else if (total > a.ws.stg_extent) {
+                    bad |= PM_F_LAYOUT;
+                }
+            }
         }
     }
 
     if (mode & kPrepZeroLb) {
-        int64_t words = ((int64_t)a.ws.pool_extent / a.tile + a.sub_count + 2) * kLbWords;
-        const int64_t cap = a.ws.max_tiles * kLbWords;
-        if (words > cap)
-            words = cap;
+        int64_t words = (int64_t)a.ws.pool_extent / a.tile + a.sub_count + 2;
+        if (words > a.ws.max_tiles)
+            words = a.ws.max_tiles;
         for (int64_t i = gtid; i < words; i += gsize)
             a.ws.lb[i] = 0ull;
     }
@@ -514,8 +628,10 @@ __global__ __launch_bounds__(1024) void k_prep(const KArgs a, int mode)
         for (int64_t i = gtid; i < (int64_t)a.sub_count * 27; i += gsize) {
             const int64_t s = a.sub_first + i / 27;
             const int d = (int)(i % 27);
-            if (d == PM_STAY)
+            if (d == PM_STAY) {
                 a.ws.stay[s] = 0;
+                a.ws.migtot[s] = 0;
+            }
             a.send.count[s * 27 + d] = 0;
         }
     }
@@ -537,7 +653,6 @@ __global__ __launch_bounds__(1024) void k_prep(const KArgs a, int mode)
         }
     }
     if (mode & kPrepCheckSend) {
-        // every source segment a destination of the range may read from
         for (int64_t i = gtid; i < (int64_t)a.dc.nsub * 27; i += gsize) {
             const int64_t b = a.send.base[i], c = a.send.cap[i];
             if (b < 0 || c < 0 || c > (int64_t)kM31 || b + c > a.ws.send_extent)
@@ -548,7 +663,24 @@ __global__ __launch_bounds__(1024) void k_prep(const KArgs a, int mode)
         flag_or(hdr, bad);
 }
 
-// The fused step: interpolate + advance + classify + scan + scatter.
+// Take the next ticket and find its tile (thread 0); false when done.
+template <int WG, int ITEMS>
+__device__ __forceinline__ bool next_tile(const KArgs &a, TileLds<WG, ITEMS> &L,
+                                          int64_t total)
+{
+    if (threadIdx.x == 0) {
+        const int64_t q = (int64_t)__hip_atomic_fetch_add(
+            a.ws.hdr + kHdrTicket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        L.h.q = q;
+        if (q < total)
+            locate(a, a.tile, q, L.h);
+    }
+    __syncthreads();
+    return L.h.q < total;
+}
+
+// The fused step: interpolate + advance + classify + scan + scatter of the
+// stayers to `out` and of the leavers to the segment's staging area.
 template <int WG, int ITEMS, typename FT, bool HALO>
 __global__ __launch_bounds__(WG) void k_step(const KArgs a)
 {
@@ -561,17 +693,7 @@ __global__ __launch_bounds__(WG) void k_step(const KArgs a)
     const int tid = threadIdx.x, w = tid >> 6;
     uint32_t fl = 0;
 
-    for (;;) {
-        if (tid == 0) {
-            const int64_t q = (int64_t)__hip_atomic_fetch_add(
-                hdr + kHdrTicket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            L.h.q = q;
-            if (q < total)
-                locate(a, a.tile, q, L.h);
-        }
-        __syncthreads();
-        if (L.h.q >= total)
-            break;
+    while (next_tile<WG, ITEMS>(a, L, total)) {
         const int s = L.h.s;
         const int64_t first = L.h.first;
         const int nitems = L.h.nitems;
@@ -583,66 +705,69 @@ __global__ __launch_bounds__(WG) void k_step(const KArgs a)
         uint64_t id[ITEMS];
         int d[ITEMS];
         uint32_t rank[ITEMS];
+        // records past the end of a ragged tile repeat the tile's last one and
+        // are dropped after classification, so no lane branches here
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const int i = k * WG + tid;
-            if (i < nitems) {
-                const int64_t p = first + i;
+            const int64_t p = first + (i < nitems ? i : nitems - 1);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    X[k][c] = a.in.x[c][p];
-                    V[k][c] = ((const FT *)a.in.v[c])[p];
-                }
-                tau[k] = ((const FT *)a.in.tau)[p];
-                id[k] = a.in.id[p];
+            for (int c = 0; c < 3; ++c) {
+                X[k][c] = a.in.x[c][p];
+                V[k][c] = ((const FT *)a.in.v[c])[p];
             }
+            tau[k] = ((const FT *)a.in.tau)[p];
+            id[k] = a.in.id[p];
         }
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             d[k] = 0xff;
             if (k * WG + tid < nitems) {
-                advance<FT, HALO>(a, X[k], V[k], tau[k], fl);
+                advance_items<FT, HALO, 1>(a, &X[k], &V[k], &tau[k], fl);
                 d[k] = classify(a.dc, own, X[k], fl);
             }
         }
 
-        tile_ranks<WG, ITEMS>(a, L, d, rank);
+        tile_ranks<WG, ITEMS>(L, d, rank);
         lookback<WG, ITEMS>(a, L);
         __syncthreads();
 
         const int64_t obase = a.out.base[s], ocap = a.out.cap[s];
+        const int64_t g0 = a.ws.stg_start[L.h.sl];
+        const int64_t gcap = a.ws.stg_start[L.h.sl + 1] - g0;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             if (d[k] == 0xff)
                 continue;
             const int b = d[k];
-            const int64_t slot = (int64_t)L.base[b] + L.cnt[b][k * NW + w] + rank[k];
+            const int e = k * NW + w;
             if (b == PM_STAY) {
+                const int64_t slot = (int64_t)L.base[0] + L.cnt[0][e] + rank[k];
                 if (slot < ocap)
                     put_record<FT>(a.out, obase + slot, X[k], V[k], tau[k], id[k]);
                 else
                     fl |= PM_F_DEST_OVERFLOW;
             } else {
-                const int64_t qq = (int64_t)s * 27 + b;
-                if (slot < a.send.cap[qq]) {
+                const int64_t m = (int64_t)L.base[1] + L.cnt[1][e] + rank[k];
+                if (m < gcap) {
                     double Xs[3];
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
                         Xs[c] = shifted(a.dc, c, own[c], dir_o(b, c), X[k][c]);
-                    put_record<FT>(a.send, a.send.base[qq] + slot, Xs, V[k], tau[k], id[k]);
+                    put_staged<FT>(a.ws, g0 + m, Xs, V[k], tau[k], id[k], b);
                 } else {
                     fl |= PM_F_SEND_OVERFLOW;
                 }
             }
         }
-        publish_totals<WG, ITEMS>(a, L);
+        publish_counts<WG, ITEMS>(a, L);
         __syncthreads();
     }
     if (fl)
         flag_or(hdr, fl);
 }
 
-// Plain path, step 1-2: in-place advance of the range's records.
+// Plain path, steps 1-2: in-place advance of the range's records.
 template <int WG, int ITEMS, typename FT, bool HALO>
 __global__ __launch_bounds__(WG) void k_advance(const KArgs a)
 {
@@ -659,34 +784,40 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs a)
         __syncthreads();
         const int64_t first = H.first;
         const int nitems = H.nitems;
+        double X[ITEMS][3];
+        FT V[ITEMS][3], tau[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int i = k * WG + tid;
+            const int64_t p = first + (i < nitems ? i : nitems - 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                X[k][c] = a.in.x[c][p];
+                V[k][c] = ((const FT *)a.in.v[c])[p];
+            }
+            tau[k] = ((const FT *)a.in.tau)[p];
+        }
+        __syncthreads();  // H is rewritten by the next tile
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const int i = k * WG + tid;
             if (i < nitems) {
+                advance_items<FT, HALO, 1>(a, &X[k], &V[k], &tau[k], fl);
                 const int64_t p = first + i;
-                double X[3];
-                FT V[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    X[c] = a.in.x[c][p];
-                    V[c] = ((const FT *)a.in.v[c])[p];
-                }
-                const FT t = ((const FT *)a.in.tau)[p];
-                advance<FT, HALO>(a, X, V, t, fl);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    a.in.x[c][p] = X[c];
-                    ((FT *)a.in.v[c])[p] = V[c];
+                    a.in.x[c][p] = X[k][c];
+                    ((FT *)a.in.v[c])[p] = V[k][c];
                 }
             }
         }
-        __syncthreads();
     }
     if (fl)
         flag_or(hdr, fl);
 }
 
-// Plain path, steps 3-4: mask, scan, pack; stayers' slots to the workspace.
+// Plain path, steps 3-4 (mask, scan): stayers' slots to the workspace,
+// leavers to the staging area in scan order.
 template <int WG, int ITEMS, typename FT>
 __global__ __launch_bounds__(WG) void k_classify(const KArgs a)
 {
@@ -699,17 +830,7 @@ __global__ __launch_bounds__(WG) void k_classify(const KArgs a)
     const int tid = threadIdx.x, w = tid >> 6;
     uint32_t fl = 0;
 
-    for (;;) {
-        if (tid == 0) {
-            const int64_t q = (int64_t)__hip_atomic_fetch_add(
-                hdr + kHdrTicket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            L.h.q = q;
-            if (q < total)
-                locate(a, a.tile, q, L.h);
-        }
-        __syncthreads();
-        if (L.h.q >= total)
-            break;
+    while (next_tile<WG, ITEMS>(a, L, total)) {
         const int s = L.h.s;
         const int64_t first = L.h.first;
         const int nitems = L.h.nitems;
@@ -730,23 +851,25 @@ __global__ __launch_bounds__(WG) void k_classify(const KArgs a)
                 d[k] = classify(a.dc, own, X[k], fl);
             }
         }
-        tile_ranks<WG, ITEMS>(a, L, d, rank);
+        tile_ranks<WG, ITEMS>(L, d, rank);
         lookback<WG, ITEMS>(a, L);
         __syncthreads();
 
+        const int64_t g0 = a.ws.stg_start[L.h.sl];
+        const int64_t gcap = a.ws.stg_start[L.h.sl + 1] - g0;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             if (d[k] == 0xff)
                 continue;
             const int b = d[k];
+            const int e = k * NW + w;
             const int64_t p = first + k * WG + tid;
-            const int64_t slot = (int64_t)L.base[b] + L.cnt[b][k * NW + w] + rank[k];
             if (b == PM_STAY) {
-                a.ws.slot[p] = (uint32_t)slot;
+                a.ws.slot[p] = L.base[0] + L.cnt[0][e] + rank[k];
             } else {
                 a.ws.slot[p] = kMigrantSlot;
-                const int64_t qq = (int64_t)s * 27 + b;
-                if (slot < a.send.cap[qq]) {
+                const int64_t m = (int64_t)L.base[1] + L.cnt[1][e] + rank[k];
+                if (m < gcap) {
                     double Xs[3];
                     FT V[3];
 #pragma unroll
@@ -754,15 +877,150 @@ __global__ __launch_bounds__(WG) void k_classify(const KArgs a)
                         Xs[c] = shifted(a.dc, c, own[c], dir_o(b, c), X[k][c]);
                         V[c] = ((const FT *)a.in.v[c])[p];
                     }
-                    put_record<FT>(a.send, a.send.base[qq] + slot, Xs, V,
-                                   ((const FT *)a.in.tau)[p], a.in.id[p]);
+                    put_staged<FT>(a.ws, g0 + m, Xs, V, ((const FT *)a.in.tau)[p], a.in.id[p],
+                                   b);
                 } else {
                     fl |= PM_F_SEND_OVERFLOW;
                 }
             }
         }
-        publish_totals<WG, ITEMS>(a, L);
+        publish_counts<WG, ITEMS>(a, L);
         __syncthreads();
+    }
+    if (fl)
+        flag_or(hdr, fl);
+}
+
+// Pack: split the staged leavers of each source segment by direction, in
+// order, into the send buffers (one workgroup per (segment, direction) job).
+// With APPEND the job is indexed by destination t and also appends to
+// out[t] after its stayers (the fused step); the (t, stay) job writes
+// out.count[t].
+template <typename FT, bool APPEND>
+__global__ __launch_bounds__(256) void k_route(const KArgs a)
+{
+    __shared__ uint32_t wcnt[4];
+    __shared__ uint32_t list[256 * 16];
+    __shared__ int64_t s_off;
+    uint32_t *hdr = a.ws.hdr;
+    if (flags_now(hdr) & PM_F_LAYOUT)
+        return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t fl = 0;
+    const int64_t jobs = (int64_t)a.sub_count * 27;
+    for (int64_t job = blockIdx.x; job < jobs; job += gridDim.x) {
+        const int x = a.sub_first + (int)(job / 27);
+        const int d = (int)(job % 27);
+        if (d == PM_STAY) {
+            if (APPEND && tid == 0) {
+                int64_t tot = a.ws.stay[x];
+                for (int dd = 0; dd < 27; ++dd) {
+                    if (dd == PM_STAY)
+                        continue;
+                    const int64_t n = a.send.count[(int64_t)neighbour(a.dc, x, dd, -1) * 27 + dd];
+                    tot += n > 0 ? n : 0;
+                }
+                a.out.count[x] = tot;
+                if (tot > a.out.cap[x])
+                    fl |= PM_F_DEST_OVERFLOW;
+            }
+            continue;
+        }
+        const int src = APPEND ? neighbour(a.dc, x, d, -1) : x;
+        const int64_t q = (int64_t)src * 27 + d;
+        const int64_t n = a.send.count[q];
+        if (n <= 0)
+            continue;
+        const int64_t scap = a.send.cap[q], sbase = a.send.base[q];
+        if (tid == 0 && n > scap)
+            fl |= PM_F_SEND_OVERFLOW;
+        const int sl = src - a.sub_first;
+        const int64_t g0 = a.ws.stg_start[sl];
+        int64_t gn = a.ws.stg_start[sl + 1] - g0;
+        if (a.ws.migtot[src] < gn)
+            gn = a.ws.migtot[src];
+        int64_t obase = 0, ocap = 0;
+        if (APPEND) {
+            if (tid == 0) {
+                int64_t off = a.ws.stay[x];
+                for (int dd = 0; dd < d; ++dd) {
+                    if (dd == PM_STAY)
+                        continue;
+                    const int64_t c = a.send.count[(int64_t)neighbour(a.dc, x, dd, -1) * 27 + dd];
+                    off += c > 0 ? c : 0;
+                }
+                s_off = off;
+            }
+            obase = a.out.base[x];
+            ocap = a.out.cap[x];
+            __syncthreads();
+        }
+        const int64_t off = APPEND ? s_off : 0;
+        int64_t run = 0;
+        // each thread takes 16 consecutive direction codes (one 16-byte load;
+        // staging areas start 16-aligned), so one pass covers 4096 leavers
+        for (int64_t i0 = 0; i0 < gn && run < n; i0 += 256 * 16) {
+            const int64_t i = i0 + (int64_t)tid * 16;
+            uint32_t m = 0;
+            if (i < gn) {
+                const uint4 q4 = *(const uint4 *)(a.ws.stg_d + g0 + i);
+                const uint32_t wd[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+                for (int b = 0; b < 16; ++b) {
+                    const uint32_t code = (wd[b >> 2] >> (8 * (b & 3))) & 0xffu;
+                    if (code == (uint32_t)d && i + b < gn)
+                        m |= 1u << b;
+                }
+            }
+            const uint32_t cnt = (uint32_t)__popc(m);
+            uint32_t incl = cnt;
+#pragma unroll
+            for (int sh = 1; sh < 64; sh <<= 1) {
+                const uint32_t t = (uint32_t)__shfl_up((int)incl, sh, 64);
+                if (lane >= sh)
+                    incl += t;
+            }
+            if (lane == 63)
+                wcnt[w] = incl;
+            __syncthreads();
+            uint32_t before = 0, tot = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t c = wcnt[k];
+                before += k < w ? c : 0u;
+                tot += c;
+            }
+            // the matches' staging indices, in order, then one copy per thread
+            uint32_t k = before + incl - cnt;
+            while (m) {
+                const int b = __ffs(m) - 1;
+                m &= m - 1;
+                list[k++] = (uint32_t)(i - i0 + b);
+            }
+            __syncthreads();
+            for (uint32_t j = tid; j < tot; j += 256) {
+                const int64_t slot = run + j;
+                if (slot < scap) {
+                    const int64_t from = g0 + i0 + list[j];
+                    double X[3];
+                    FT V[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        X[c] = a.ws.stg_x[c][from];
+                        V[c] = ((const FT *)a.ws.stg_v[c])[from];
+                    }
+                    const FT t = ((const FT *)a.ws.stg_tau)[from];
+                    const uint64_t idv = a.ws.stg_id[from];
+                    put_record<FT>(a.send, sbase + slot, X, V, t, idv);
+                    if (APPEND && off + slot < ocap)
+                        put_record<FT>(a.out, obase + off + slot, X, V, t, idv);
+                }
+            }
+            run += tot;
+            __syncthreads();
+        }
+        if (APPEND)
+            __syncthreads();  // s_off is rewritten by the next job
     }
     if (fl)
         flag_or(hdr, fl);
@@ -816,8 +1074,9 @@ __global__ __launch_bounds__(WG) void k_compact(const KArgs a)
         flag_or(hdr, fl);
 }
 
-// Receive: append what every destination t of the range receives after its
-// stayers, direction code ascending, each buffer in order (unpacking).
+// Plain path, unpacking part 2: what every destination t of the range
+// receives, after its stayers, direction code ascending, each send buffer
+// in order.
 template <typename FT>
 __global__ __launch_bounds__(256) void k_append(const KArgs a)
 {
@@ -834,16 +1093,7 @@ __global__ __launch_bounds__(256) void k_append(const KArgs a)
         if (tid < 27) {
             int64_t n = 0, st = 0, sb = 0;
             if (tid != PM_STAY) {
-                int tt[3];
-                owner_xyz(a.dc, t, tt);
-                int sc[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int P = a.dc.p[c];
-                    sc[c] = ((tt[c] - dir_o(tid, c)) % P + P) % P;
-                }
-                const int64_t src = sc[0] + (int64_t)a.dc.p[0] * (sc[1] + (int64_t)a.dc.p[1] * sc[2]);
-                const int64_t qq = src * 27 + tid;
+                const int64_t qq = (int64_t)neighbour(a.dc, t, tid, -1) * 27 + tid;
                 n = a.send.count[qq];
                 n = n < 0 ? 0 : n;
                 const int64_t cp = a.send.cap[qq];
@@ -992,10 +1242,16 @@ bool shape_supported(Shape sh)
 
 hipError_t launch_prep(const KArgs &a, int mode, hipStream_t st)
 {
-    int grid = 1;
-    if (mode & (kPrepZeroLb | kPrepZeroCounts | kPrepCheckSend | kPrepCheckIn | kPrepCheckOut))
-        grid = 256;
-    hipLaunchKernelGGL(k_prep, dim3(grid), dim3(1024), 0, st, a, mode);
+    int64_t work = 1;
+    if (mode & kPrepZeroLb)
+        work = (int64_t)a.ws.pool_extent / a.tile + a.sub_count + 2;
+    if (mode & (kPrepZeroCounts | kPrepCheckSend))
+        work = work > (int64_t)a.dc.nsub * 27 ? work : (int64_t)a.dc.nsub * 27;
+    if (mode & kPrepZeroCounts)
+        work = work > (int64_t)a.sub_count * 27 ? work : (int64_t)a.sub_count * 27;
+    int64_t g = (work + 1023) / 1024;
+    const int grid = (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+    hipLaunchKernelGGL(k_prep, dim3(grid), dim3(256), 0, st, a, mode);
     return hipGetLastError();
 }
 
@@ -1082,6 +1338,24 @@ hipError_t launch_append(const KArgs &a, bool mixed, int grid, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_route(const KArgs &a, bool mixed, bool append, hipStream_t st)
+{
+    const int64_t jobs = (int64_t)a.sub_count * 27;
+    const int grid = (int)(jobs < 4096 ? jobs : 4096);
+    if (mixed) {
+        if (append)
+            hipLaunchKernelGGL((k_route<float, true>), dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_route<float, false>), dim3(grid), dim3(256), 0, st, a);
+    } else {
+        if (append)
+            hipLaunchKernelGGL((k_route<double, true>), dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_route<double, false>), dim3(grid), dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_interp(const KArgs &a, bool mixed, int64_t n, const double *x,
                          const double *y, const double *z, void *ux, void *uy, void *uz,
                          hipStream_t st)
@@ -1140,13 +1414,17 @@ hipError_t launch_fill(uint64_t *p, int64_t words, hipStream_t st)
 
 #define PM_OCC_CASE(W, I)                                                              \
     if (sh.wg == W && sh.items == I) {                                                 \
-        if (mixed)                                                                     \
+        if (mixed && halo)                                                             \
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, float, true>), W, 0); \
+        else if (mixed)                                                                \
             (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, float, false>), W, 0); \
+        else if (halo)                                                                 \
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, double, true>), W, 0); \
         else                                                                           \
             (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, double, false>), W, 0); \
     }
 
-int step_occupancy(Shape sh, bool mixed)
+int step_occupancy(Shape sh, bool mixed, bool halo)
 {
     int nb = 1;
     PM_SHAPES(PM_OCC_CASE)

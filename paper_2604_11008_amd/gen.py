@@ -295,15 +295,29 @@ def send_layout(counts, face=0.02, edge=0.002, corner=0.0005, extra=256):
     return base, cap
 
 
+def morton3(i, j, k, bits=11):
+    """Z-order code of cell (i, j, k): bits of i, j, k interleaved, i lowest."""
+    code = np.zeros(np.shape(i), dtype=np.int64)
+    for b in range(bits):
+        code |= ((np.asarray(i, dtype=np.int64) >> b) & 1) << (3 * b)
+        code |= ((np.asarray(j, dtype=np.int64) >> b) & 1) << (3 * b + 1)
+        code |= ((np.asarray(k, dtype=np.int64) >> b) & 1) << (3 * b + 2)
+    return code
+
+
 def build_pool(pos, tau, ids, p, bnds, n, L=TWO_PI, slack=0.05, extra=1024,
                vdtype=np.float64, order="canonical", shuffle_seed=None):
     """Pool with each particle in its owner's segment.  Canonical order: by
-    subdomain, then cell (z, y, x), then id.  order="shuffled" permutes each
-    segment with the shuffle seed."""
+    subdomain, then the Z-order (Morton) code of the cell, then id.
+    order="rowmajor" sorts by cell (z, y, x) instead; order="shuffled"
+    permutes each segment of the canonical order with the shuffle seed."""
     nsub = p[0] * p[1] * p[2]
     s = owner(pos, bnds, p)
     cell = [np.clip(np.floor(pos[a] * (n / L)).astype(np.int64), 0, n - 1) for a in range(3)]
-    perm = np.lexsort((ids, cell[0], cell[1], cell[2], s))
+    if order == "rowmajor":
+        perm = np.lexsort((ids, cell[0], cell[1], cell[2], s))
+    else:
+        perm = np.lexsort((ids, morton3(cell[0], cell[1], cell[2]), s))
     s_sorted = s[perm]
     counts = np.bincount(s_sorted, minlength=nsub).astype(np.int64)
     if order == "shuffled":

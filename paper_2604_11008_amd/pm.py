@@ -73,7 +73,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
-            "pm_workspace_bytes": ([i64, i32], C.c_size_t),
+            "pm_workspace_bytes": ([i64, i64, i32], C.c_size_t),
             "pm_create": ([vp, vp, C.c_size_t, i64, i64, i32], C.c_int),
             "pm_destroy": ([vp], C.c_int),
             "pm_interp": ([vp, vp, i64, vp, vp, vp, vp, vp, vp, vp], C.c_int),
@@ -254,8 +254,8 @@ class Params:
         return _Params(float(self.dt), (C.c_double * 3)(*[float(x) for x in self.g]))
 
 
-def workspace_bytes(pool_extent, nsub):
-    return int(lib().pm_workspace_bytes(int(pool_extent), int(nsub)))
+def workspace_bytes(pool_extent, send_extent, nsub):
+    return int(lib().pm_workspace_bytes(int(pool_extent), int(send_extent), int(nsub)))
 
 
 class Context:
@@ -265,7 +265,7 @@ class Context:
         self.pool_extent = int(pool_extent)
         self.send_extent = int(send_extent)
         self.nsub = int(nsub)
-        nb = workspace_bytes(self.pool_extent, self.nsub)
+        nb = workspace_bytes(self.pool_extent, self.send_extent, self.nsub)
         self.workspace = torch.empty(nb, dtype=torch.uint8, device=device)
         h = C.c_void_p()
         _check(lib().pm_create(C.byref(h), _p(self.workspace), nb, self.pool_extent,

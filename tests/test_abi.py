@@ -43,8 +43,8 @@ def test_binding_struct_layout_matches_header():
 def test_host_only_calls():
     from paper_2604_11008_amd import pm
     lib = pm.lib()
-    assert lib.pm_workspace_bytes(1 << 20, 8) > (1 << 20) * 4
-    assert lib.pm_workspace_bytes(-1, 8) == 0
+    assert lib.pm_workspace_bytes(1 << 20, 1 << 16, 8) > (1 << 20) * 4 + (1 << 16) * 65
+    assert lib.pm_workspace_bytes(-1, 0, 8) == 0
     h = ctypes.c_void_p()
     # argument errors are reported without touching a device
     assert lib.pm_create(ctypes.byref(h), None, 0, 100, 100, 0) == 1

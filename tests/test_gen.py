@@ -60,7 +60,7 @@ def test_pool_layout_and_canonical_order():
         assert np.all((x >= 0) & (x < wl.L))
         np.testing.assert_array_equal(gen.owner(x, wl.bounds, wl.p), s)
         cell = np.floor(x * (wl.n / wl.L)).astype(np.int64)
-        key = cell[0] + wl.n * (cell[1] + wl.n * cell[2])
+        key = gen.morton3(cell[0], cell[1], cell[2])
         assert np.all(np.diff(key) >= 0)
 
 
