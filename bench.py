@@ -182,6 +182,25 @@ def main():
                 "algorithmic_bytes_per_launch": alg["fused_kernel"]}
 
     extra = {}
+    if not args.graph:
+        # the same steps replayed from captured HIP graphs (two graphs: A->B, B->A)
+        ctx.set_timing(0)
+        ctx.set_graph(True)
+        for _ in range(2):
+            ctx.step(field, dc, pa, pb, send, params)
+            pa, pb = pb, pa
+        torch.cuda.synchronize()
+        tg0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.step(field, dc, pa, pb, send, params)
+            pa, pb = pb, pa
+        torch.cuda.synchronize()
+        tg1 = time.perf_counter()
+        ctx.set_graph(False)
+        f = ctx.get_status()
+        if f:
+            raise SystemExit(f"flags after graph steps: {pm.flag_names(f)}")
+        extra["graph_ms_per_step"] = round((tg1 - tg0) * 1e3 / args.steps, 5)
     if args.plain:
         ctx.set_timing(0)
         sendp = pm.DevicePool.empty(sb, sc, vdtype=vdt, device=dev)
