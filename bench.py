@@ -57,8 +57,13 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain torch copy of 1 GiB (PMC scaling reference)")
     ap.add_argument("--traffic", default=None,
-                    help="JSON with measured fetch/write bytes per fused launch")
+                    help="traffic record of the fused kernel (default: "
+                         "profiles/k_step_<config>_traffic.json)")
     ap.add_argument("--plain", action="store_true", help="time the 3-call plain path too")
+    ap.add_argument("--side-stream", action="store_true",
+                    help="run on a new (default-priority) stream instead of the null stream")
+    ap.add_argument("--plain-per-sub", action="store_true",
+                    help="time the plain path launched once per subdomain")
     return ap.parse_args()
 
 
@@ -87,6 +92,42 @@ def cpu_baseline(wl, seconds):
                       f"({npart} particles each, sequential FP64, one thread), {el:.1f} s"}
 
 
+def single_core_triad_gbps(nbytes=1 << 28, reps=5):
+    """a = b + s*c on one core (numpy, float64): 3 arrays x nbytes/8 values."""
+    n = nbytes // 8
+    b = np.full(n, 1.5)
+    c = np.full(n, 0.25)
+    a = np.empty_like(b)
+    best = 1e30
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        np.multiply(c, 3.0, out=a)
+        np.add(a, b, out=a)
+        best = min(best, time.perf_counter() - t0)
+    # the two passes move 5 arrays (c, a | a, b, a); the triad counts 3
+    return 3 * nbytes / (best * 5 / 3) / 1e9
+
+
+def link_gbps(torch, dev, nbytes=1 << 28):
+    """Pinned host <-> device copy rates (GB/s)."""
+    h = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        d.copy_(h, non_blocking=True)
+        h.copy_(d, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(4):
+        d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(4):
+        h.copy_(d, non_blocking=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return 4 * nbytes / (t1 - t0) / 1e9, 4 * nbytes / (t2 - t1) / 1e9
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -101,8 +142,14 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.side_stream:
+        torch.cuda.set_stream(torch.cuda.Stream(device=dev))
     t_gen = time.perf_counter()
-    wl = gen.make_workload(args.config)
+    big = gen.CONFIGS[args.config]["n"] >= 512
+    multi = np.prod(gen.CONFIGS[args.config]["p"]) > 1
+    # subdomain counts random-walk as particles migrate: leave room to grow
+    wl = gen.make_workload(args.config, field_backend="device" if big else "numpy",
+                           slack=0.25 if multi else 0.05, extra=4096 if multi else 1024)
     t_gen = time.perf_counter() - t_gen
     mixed = wl.mode == "mixed"
     fdt = np.float32 if mixed else np.float64
@@ -171,9 +218,15 @@ def main():
     roof = None
     if k_ms:
         achieved = alg["fused_kernel"] / (k_ms * 1e-3) / 1e9
+        from paper_2604_11008_amd import profsum
+        wg, items, _ = ctx.get_tuning()
+        variant = (f"k_step<{wg}, {items}, {'float' if mixed else 'double'}, "
+                   f"{'true' if wl.halo else 'false'}>")
+        tpath = args.traffic or os.path.join(ROOT, "profiles",
+                                             f"k_step_{args.config}_traffic.json")
         traffic = None
-        if args.traffic and os.path.exists(args.traffic):
-            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+        if os.path.exists(tpath) and json.load(open(tpath)).get("kernel") == variant:
+            traffic = profsum.load_traffic(tpath)
         roof = {"bound": "hbm", "achieved": round(achieved, 1),
                 "peak": accounting.HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / accounting.HBM_PEAK_GBPS, 4), "traffic": traffic,
@@ -220,6 +273,28 @@ def main():
         tp1 = time.perf_counter()
         extra["plain_ms_per_step_incl_copy"] = round((tp1 - tp0) * 1e3 / args.steps, 4)
 
+    if args.plain_per_sub:
+        ctx.set_timing(0)
+        sendp = pm.DevicePool.empty(sb, sc, vdtype=vdt, device=dev)
+        work = pm.DevicePool.empty(pool.base, pool.cap, vdtype=vdt, device=dev, size=size)
+        steps = max(1, min(args.steps, 5))
+        torch.cuda.synchronize()
+        tq0 = time.perf_counter()
+        for _ in range(steps):
+            work.x.copy_(pa.x)
+            work.v.copy_(pa.v)
+            work.tau.copy_(pa.tau)
+            work.id.copy_(pa.id)
+            work.count.copy_(pa.count)
+            for s in range(dc.nsub):
+                ctx.interp_advance(field, work, params, s, 1)
+            for s in range(dc.nsub):
+                ctx.classify_scan_pack(dc, work, sendp, s, 1)
+            for s in range(dc.nsub):
+                ctx.compact_append(dc, work, sendp, pb, s, 1)
+        torch.cuda.synchronize()
+        tq1 = time.perf_counter()
+        extra["plain_per_subdomain_ms_per_step_incl_copy"] = round((tq1 - tq0) * 1e3 / steps, 4)
     if args.copy_probe:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
@@ -239,6 +314,17 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_seconds)
+        # the paper's CPU-delegated estimate (Sect. 3.2.2) for this host and workload:
+        # arrays out and back over the link, packed and unpacked at one core's bandwidth
+        h2d, d2h = link_gbps(torch, dev)
+        triad = single_core_triad_gbps()
+        model = accounting.cpu_delegated_model(1, accounting.record_bytes(
+            "mixed" if mixed else "f64"), npart, min(h2d, d2h), triad)
+        extra["cpu_delegated_model"] = {
+            "link_GBps_h2d": round(h2d, 1), "link_GBps_d2h": round(d2h, 1),
+            "single_core_triad_GBps": round(triad, 1),
+            "ms_per_migration": round(model["total_ms"], 2),
+            "gpu_fused_step_ms": round(ms_step, 4)}
 
     value = npart / (ms_step * 1e-3)
     line = {

@@ -203,56 +203,44 @@ template <typename FT> __device__ __forceinline__ FT kg(const KArgs &a, int c);
 template <> __device__ __forceinline__ double kg<double>(const KArgs &a, int c) { return a.g[c]; }
 template <> __device__ __forceinline__ float kg<float>(const KArgs &a, int c) { return a.gf[c]; }
 
-// Heun step of N particles, phase by phase: stage-1 indices, stage-1 loads,
-// stage-1 updates and stage-2 indices, stage-2 loads of the stencils that
-// changed cell, final update.  Each particle's arithmetic does not depend on
-// N.  The kernels use N = 1 per record: batching several records this way
-// needs 24 stencil values per record in registers at once, and the lost
-// occupancy costs more than the overlap gains.
-template <typename FT, bool HALO, int N>
-__device__ __forceinline__ void advance_items(const KArgs &a, double (*X)[3], FT (*V)[3],
-                                              const FT *tau, uint32_t &fl)
+// Heun step of one particle.  The stage-2 position X* = X + dt V does not
+// depend on the stage-1 interpolation, so both stencils are located first
+// and fetched in one round trip; most stage-2 stencils fall in the stage-1
+// cell and are not fetched again.
+template <typename FT, bool HALO>
+__device__ __forceinline__ void advance_one(const KArgs &a, double X[3], FT V[3], FT tau,
+                                            uint32_t &fl)
 {
     const FT dt = kdt<FT>(a), hdt = khdt<FT>(a);
-    int c1[N][3], c2[N][3];
-    FT fr[N][3], S[N][3][8], A1[N][3], Vs[N][3], it[N];
-    bool moved[N];
+    int c1[3], c2[3];
+    FT fr1[3], fr2[3], S1[3][8], S2[3][8];
+    double Xs[3];
 #pragma unroll
-    for (int k = 0; k < N; ++k)
-        stencil_index<FT, HALO>(a.f, X[k], c1[k], fr[k], fl);
+    for (int c = 0; c < 3; ++c)
+        Xs[c] = fma(a.dt, (double)V[c], X[c]);
+    stencil_index<FT, HALO>(a.f, X, c1, fr1, fl);
+    stencil_index<FT, HALO>(a.f, Xs, c2, fr2, fl);
+    const bool moved = c2[0] != c1[0] || c2[1] != c1[1] || c2[2] != c1[2];
+    stencil_load<FT, HALO>(a.f, c1, S1);
+    if (moved)
+        stencil_load<FT, HALO>(a.f, c2, S2);
+    FT U1[3], A1[3], Vs[3], U2[3];
+    stencil_eval<FT>(S1, fr1, U1);
+    const FT it = (FT)1 / tau;
 #pragma unroll
-    for (int k = 0; k < N; ++k)
-        stencil_load<FT, HALO>(a.f, c1[k], S[k]);
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        FT U1[3];
-        double Xs[3];
-        stencil_eval<FT>(S[k], fr[k], U1);
-        it[k] = (FT)1 / tau[k];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            A1[k][c] = fma(U1[c] - V[k][c], it[k], kg<FT>(a, c));
-            Xs[c] = fma(a.dt, (double)V[k][c], X[k][c]);
-            Vs[k][c] = fma(dt, A1[k][c], V[k][c]);
-        }
-        stencil_index<FT, HALO>(a.f, Xs, c2[k], fr[k], fl);
-        moved[k] = c2[k][0] != c1[k][0] || c2[k][1] != c1[k][1] || c2[k][2] != c1[k][2];
+    for (int c = 0; c < 3; ++c) {
+        A1[c] = fma(U1[c] - V[c], it, kg<FT>(a, c));
+        Vs[c] = fma(dt, A1[c], V[c]);
     }
-    // stage 2 mostly falls in the same cell, whose node values are loaded
+    if (moved)
+        stencil_eval<FT>(S2, fr2, U2);
+    else
+        stencil_eval<FT>(S1, fr2, U2);
 #pragma unroll
-    for (int k = 0; k < N; ++k)
-        if (moved[k])
-            stencil_load<FT, HALO>(a.f, c2[k], S[k]);
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        FT U2[3];
-        stencil_eval<FT>(S[k], fr[k], U2);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const FT A2 = fma(U2[c] - Vs[k][c], it[k], kg<FT>(a, c));
-            X[k][c] = fma(a.half_dt, (double)V[k][c] + (double)Vs[k][c], X[k][c]);
-            V[k][c] = fma(hdt, A1[k][c] + A2, V[k][c]);
-        }
+    for (int c = 0; c < 3; ++c) {
+        const FT A2 = fma(U2[c] - Vs[c], it, kg<FT>(a, c));
+        X[c] = fma(a.half_dt, (double)V[c] + (double)Vs[c], X[c]);
+        V[c] = fma(hdt, A1[c] + A2, V[c]);
     }
 }
 
@@ -723,7 +711,7 @@ __global__ __launch_bounds__(WG) void k_step(const KArgs a)
         for (int k = 0; k < ITEMS; ++k) {
             d[k] = 0xff;
             if (k * WG + tid < nitems) {
-                advance_items<FT, HALO, 1>(a, &X[k], &V[k], &tau[k], fl);
+                advance_one<FT, HALO>(a, X[k], V[k], tau[k], fl);
                 d[k] = classify(a.dc, own, X[k], fl);
             }
         }
@@ -802,7 +790,7 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs a)
         for (int k = 0; k < ITEMS; ++k) {
             const int i = k * WG + tid;
             if (i < nitems) {
-                advance_items<FT, HALO, 1>(a, &X[k], &V[k], &tau[k], fl);
+                advance_one<FT, HALO>(a, X[k], V[k], tau[k], fl);
                 const int64_t p = first + i;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {

@@ -132,6 +132,32 @@ def spectral_field(n: int, k0: float, kmax: int, seed, backend: str = "numpy"):
     return [u * scale for u in comps]
 
 
+def spectral_field_device(n: int, k0: float, kmax: int, seed, device="cuda"):
+    """spectral_field computed with torch on a device: the same modes and
+    phases, the inverse transform and scaling done there.  Returns three
+    float64 device tensors (n,n,n)."""
+    import torch
+    if kmax > n // 2 - 1:
+        raise ValueError("kmax must stay below the Nyquist wavenumber")
+    kv, uh = spectral_modes(k0, kmax, seed)
+    phase = np.exp(1j * math.pi * kv.sum(axis=1) / n)
+    iz = torch.from_numpy(np.concatenate([kv[:, 2] % n, (-kv[:, 2]) % n])).to(device)
+    iy = torch.from_numpy(np.concatenate([kv[:, 1] % n, (-kv[:, 1]) % n])).to(device)
+    ix = torch.from_numpy(np.concatenate([kv[:, 0] % n, (-kv[:, 0]) % n])).to(device)
+    comps = []
+    for c in range(3):
+        val = uh[:, c] * phase
+        vals = torch.from_numpy(np.concatenate([val, np.conj(val)])).to(device)
+        spec = torch.zeros((n, n, n), dtype=torch.complex128, device=device)
+        spec[iz, iy, ix] = vals
+        u = torch.fft.ifftn(spec).real.mul_(float(n) ** 3).contiguous()
+        del spec
+        comps.append(u)
+    ms = sum(float((u * u).mean()) for u in comps) / 3.0
+    scale = 1.0 / math.sqrt(ms)
+    return [u.mul_(scale) for u in comps]
+
+
 def with_halo(u: np.ndarray) -> np.ndarray:
     """Periodic copy of one cell on each side: (n+2)^3."""
     return np.pad(u, 1, mode="wrap")
@@ -269,10 +295,28 @@ def empty_pool(base, cap, vdtype=np.float64):
                 base=base, cap=cap, count=np.zeros(len(base), dtype=np.int64))
 
 
-def layout(counts, slack=0.05, extra=1024, align=64):
-    """Segment bases and capacities with room for growth, in subdomain order."""
+def neighbour_max(counts, p):
+    """Largest count among the 26 periodic neighbours of every subdomain."""
+    c = np.asarray(counts).reshape(p[2], p[1], p[0])
+    m = np.zeros_like(c)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx or dy or dz:
+                    m = np.maximum(m, np.roll(c, (dz, dy, dx), axis=(0, 1, 2)))
+    return m.reshape(-1)
+
+
+def layout(counts, slack=0.05, extra=1024, align=64, p=None, inflow=0.05):
+    """Segment bases and capacities with room for growth, in subdomain order.
+    With the decomposition p, a segment also gets room for `inflow` times its
+    most populated neighbour (uneven counts make particles flow into the
+    sparse subdomains)."""
     counts = np.asarray(counts, dtype=np.int64)
-    cap = ((counts * (1.0 + slack)).astype(np.int64) + extra + align - 1) // align * align
+    grow = counts * (1.0 + slack)
+    if p is not None and int(np.prod(p)) > 1:
+        grow = grow + inflow * neighbour_max(counts, p)
+    cap = (grow.astype(np.int64) + extra + align - 1) // align * align
     base = np.zeros_like(cap)
     base[1:] = np.cumsum(cap)[:-1]
     return base, cap
@@ -327,7 +371,7 @@ def build_pool(pos, tau, ids, p, bnds, n, L=TWO_PI, slack=0.05, extra=1024,
             c = int(counts[q])
             perm[start:start + c] = perm[start:start + c][g.permutation(c)]
             start += c
-    base, cap = layout(counts, slack=slack, extra=extra)
+    base, cap = layout(counts, slack=slack, extra=extra, p=p)
     pool = empty_pool(base, cap, vdtype)
     start = 0
     for q in range(nsub):
@@ -359,11 +403,22 @@ class Workload:
     info: dict = dc_field(default_factory=dict)
 
     def stored_field(self, dtype=np.float64):
-        """Field arrays as stored on the device (with the halo if any)."""
+        """Field arrays as stored on the device (with the halo if any): numpy
+        arrays, or device tensors when the field was generated on a device."""
         out = []
         for u in self.field:
-            a = with_halo(u) if self.halo else u
-            out.append(np.ascontiguousarray(a.astype(dtype)).reshape(-1))
+            if isinstance(u, np.ndarray):
+                a = with_halo(u) if self.halo else u
+                out.append(np.ascontiguousarray(a.astype(dtype)).reshape(-1))
+            else:
+                import torch
+                a = u
+                if self.halo:
+                    a = torch.cat([a[-1:], a, a[:1]], dim=0)
+                    a = torch.cat([a[:, -1:], a, a[:, :1]], dim=1)
+                    a = torch.cat([a[:, :, -1:], a, a[:, :, :1]], dim=2)
+                tdt = torch.float32 if dtype == np.float32 else torch.float64
+                out.append(a.to(tdt).contiguous().reshape(-1))
         return out
 
 
@@ -374,7 +429,10 @@ def dt_rule(field, tau_max, g, n, L=TWO_PI, kind="rule"):
     gn = math.sqrt(sum(c * c for c in g))
     if kind == "rms":
         return 0.5 * delta
-    umax = math.sqrt(float(np.max(field[0] ** 2 + field[1] ** 2 + field[2] ** 2)))
+    if isinstance(field[0], np.ndarray):
+        umax = math.sqrt(float(np.max(field[0] ** 2 + field[1] ** 2 + field[2] ** 2)))
+    else:
+        umax = math.sqrt(float((field[0] ** 2 + field[1] ** 2 + field[2] ** 2).max()))
     return 0.5 * delta / (umax + tau_max * gn)
 
 
@@ -389,7 +447,10 @@ def make_workload(name, np_override=None, n_override=None, p_override=None,
     kmax = kmax_override or min(cfg["kmax"], n // 2 - 1)
     s_field, s_pos, s_tau, s_shuf = seeds(cfg["index"])
     L = TWO_PI
-    field = spectral_field(n, k0, kmax, s_field, backend=field_backend)
+    if field_backend == "device":
+        field = spectral_field_device(n, k0, kmax, s_field)
+    else:
+        field = spectral_field(n, k0, kmax, s_field, backend=field_backend)
     bnds = bounds(p, L)
     gp = rng(s_pos)
     npart = np_override or cfg["np"]
