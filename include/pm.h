@@ -150,7 +150,9 @@ typedef struct {
 
 /* Launch shape of the tile kernels: workgroup size (256 or 512), records
  * per thread (1, 2, 4 or 8); tile = wg*items records.  blocks_per_cu is the
- * persistent grid's workgroups per compute unit (0 = as many as fit). */
+ * persistent grid's workgroups per compute unit: 0 = the runtime's occupancy
+ * estimate; an explicit 1..32 may exceed it (surplus workgroups start as
+ * others retire; tiles are claimed by ticket, so this cannot deadlock). */
 typedef struct {
     int32_t wg;
     int32_t items;

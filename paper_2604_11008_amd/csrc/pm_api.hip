@@ -246,8 +246,12 @@ pm_status check_range(pm_ctx *ctx, int32_t nsub, int32_t first, int32_t count)
 
 int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed, bool halo)
 {
-    const int occ = pm::step_occupancy(sh, mixed, halo);
-    const int per = ctx->blocks_per_cu > 0 ? std::min(ctx->blocks_per_cu, occ) : occ;
+    // An explicit figure may exceed the runtime's occupancy estimate: workgroups
+    // that do not fit start as others retire, and since tiles are claimed by
+    // ticket when a workgroup runs, no running workgroup waits on one that has
+    // not started.
+    const int per = ctx->blocks_per_cu > 0 ? ctx->blocks_per_cu
+                                           : pm::step_occupancy(sh, mixed, halo);
     return std::max(1, ctx->cus * per);
 }
 
@@ -715,7 +719,7 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
     }
     const pm::Shape shapes[] = {{256, 1}, {256, 2}, {256, 4}, {256, 8},
                                 {512, 1}, {512, 2}, {512, 4}};
-    const int bpcs[] = {0, 1, 2};
+    const int bpcs[] = {0, 2, 3, 4, 6};
     const bool was_graph = ctx->use_graph;
     const int32_t was_tmax = ctx->tmax;
     ctx->use_graph = false;
@@ -728,8 +732,6 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
     int best_bpc = ctx->blocks_per_cu;
     for (const auto &sh : shapes) {
         for (int bpc : bpcs) {
-            if (bpc > pm::step_occupancy(sh, mixed, k.f.halo != 0))
-                continue;
             ctx->shape = sh;
             ctx->blocks_per_cu = bpc;
             pm::KArgs kk = k;

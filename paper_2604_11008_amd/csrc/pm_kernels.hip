@@ -452,6 +452,58 @@ __device__ __forceinline__ void lookback(const KArgs &a, TileLds<WG, ITEMS> &L)
     }
 }
 
+// The two halves of lookback() for the fused kernel, which publishes a
+// tile's aggregate as soon as its counts are known and walks back later.
+template <int WG, int ITEMS>
+__device__ __forceinline__ void publish_aggregate(const KArgs &a, const TileLds<WG, ITEMS> &L)
+{
+    if (threadIdx.x == 0) {
+        const uint64_t agg = (uint64_t)L.agg[0] | ((uint64_t)L.agg[1] << 31);
+        lb_store(a.ws.lb + L.h.q, (L.h.q == L.h.qhead ? kLbP : kLbA) | agg);
+    }
+}
+
+template <int WG, int ITEMS>
+__device__ __forceinline__ void walk_back(const KArgs &a, TileLds<WG, ITEMS> &L)
+{
+    const int lane = threadIdx.x;
+    if (lane >= 64)
+        return;
+    const TileHead &h = L.h;
+    uint64_t excl = 0;
+    if (h.q != h.qhead) {
+        const uint64_t *lb = a.ws.lb;
+        int64_t pb = h.q - 1;
+        for (;;) {
+            const int64_t t = pb - lane;
+            uint64_t v = kLbP;  // before the segment's first tile: a zero prefix
+            if (t >= h.qhead) {
+                v = lb_load(lb + t);
+                while ((v >> 62) == 0ull) {
+                    __builtin_amdgcn_s_sleep(1);
+                    v = lb_load(lb + t);
+                }
+            }
+            const uint64_t pmask = __ballot((v >> 62) == 2ull);
+            if (pmask) {
+                const int k = __ffsll((unsigned long long)pmask) - 1;
+                excl += wave_sum64(lane <= k ? (v & kLbMask) : 0ull);
+                break;
+            }
+            excl += wave_sum64(v & kLbMask);
+            pb -= 64;
+        }
+        if (lane == 0) {
+            const uint64_t agg = (uint64_t)L.agg[0] | ((uint64_t)L.agg[1] << 31);
+            lb_store(a.ws.lb + h.q, kLbP | (excl + agg));
+        }
+    }
+    if (lane == 0) {
+        L.base[0] = (uint32_t)(excl & kM31);
+        L.base[1] = (uint32_t)((excl >> 31) & kM31);
+    }
+}
+
 // After the scatter: per-direction leaver counts of the tile into the
 // segment's send counts, and the segment totals from its last tile.
 template <int WG, int ITEMS>
@@ -667,24 +719,92 @@ __device__ __forceinline__ bool next_tile(const KArgs &a, TileLds<WG, ITEMS> &L,
     return L.h.q < total;
 }
 
+// Records of a tile between its advance and its scatter.  Each thread keeps
+// its own entries (index k*WG + tid), so no barrier guards them.  Leavers
+// are kept with their positions already shifted into the receiver's frame.
+template <int WG, int ITEMS, typename FT>
+struct TileStash {
+    static constexpr int T = WG * ITEMS;
+    double x[3][T];
+    FT v[3][T];
+    FT tau[T];
+    uint64_t id[T];
+    uint32_t code[T];  // (slot among the tile's stayers or leavers) << 8 | direction
+};
+
+// Scatter of a stashed tile once its offsets are known: stayers to `out`,
+// leavers to the segment's staging area; then its counts.
+template <int WG, int ITEMS, typename FT>
+__device__ __forceinline__ void scatter_stash(const KArgs &a, const TileLds<WG, ITEMS> &L,
+                                              const TileStash<WG, ITEMS, FT> &S, uint32_t &fl)
+{
+    const int tid = threadIdx.x;
+    const int s = L.h.s;
+    const int64_t obase = a.out.base[s], ocap = a.out.cap[s];
+    const int64_t g0 = a.ws.stg_start[L.h.sl];
+    const int64_t gcap = a.ws.stg_start[L.h.sl + 1] - g0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int i = k * WG + tid;
+        const uint32_t code = S.code[i];
+        const int b = (int)(code & 0xffu);
+        if (b == 0xff)
+            continue;
+        double X[3];
+        FT V[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            X[c] = S.x[c][i];
+            V[c] = S.v[c][i];
+        }
+        const FT tau = S.tau[i];
+        const uint64_t id = S.id[i];
+        if (b == PM_STAY) {
+            const int64_t slot = (int64_t)L.base[0] + (code >> 8);
+            if (slot < ocap)
+                put_record<FT>(a.out, obase + slot, X, V, tau, id);
+            else
+                fl |= PM_F_DEST_OVERFLOW;
+        } else {
+            const int64_t m = (int64_t)L.base[1] + (code >> 8);
+            if (m < gcap)
+                put_staged<FT>(a.ws, g0 + m, X, V, tau, id, b);
+            else
+                fl |= PM_F_SEND_OVERFLOW;
+        }
+    }
+    publish_counts<WG, ITEMS>(a, L);
+}
+
 // The fused step: interpolate + advance + classify + scan + scatter of the
 // stayers to `out` and of the leavers to the segment's staging area.
+//
+// Software-pipelined over the workgroup's tiles: a tile's aggregate is
+// published as soon as its counts are known, its records go to the LDS
+// stash, and its look-back and scatter run after the workgroup has advanced
+// its next tile.  By then the tiles before it have (almost always) published
+// their aggregates, so the look-back does not wait on slower neighbours.
+// A tile's aggregate never waits on anything, so every walk ends.
 template <int WG, int ITEMS, typename FT, bool HALO>
 __global__ __launch_bounds__(WG) void k_step(const KArgs a)
 {
     constexpr int NW = WG / 64;
-    __shared__ TileLds<WG, ITEMS> L;
+    __shared__ TileLds<WG, ITEMS> L[2];
+    __shared__ TileStash<WG, ITEMS, FT> S;
     uint32_t *hdr = a.ws.hdr;
     if (flags_now(hdr) & PM_F_LAYOUT)
         return;
     const int64_t total = hdr[kHdrTiles];
     const int tid = threadIdx.x, w = tid >> 6;
     uint32_t fl = 0;
+    int cur = 0;
+    bool pend = false;
 
-    while (next_tile<WG, ITEMS>(a, L, total)) {
-        const int s = L.h.s;
-        const int64_t first = L.h.first;
-        const int nitems = L.h.nitems;
+    while (next_tile<WG, ITEMS>(a, L[cur], total)) {
+        TileLds<WG, ITEMS> &C = L[cur];
+        const int s = C.h.s;
+        const int64_t first = C.h.first;
+        const int nitems = C.h.nitems;
         int own[3];
         owner_xyz(a.dc, s, own);
 
@@ -716,40 +836,50 @@ __global__ __launch_bounds__(WG) void k_step(const KArgs a)
             }
         }
 
-        tile_ranks<WG, ITEMS>(L, d, rank);
-        lookback<WG, ITEMS>(a, L);
-        __syncthreads();
+        tile_ranks<WG, ITEMS>(C, d, rank);
+        publish_aggregate<WG, ITEMS>(a, C);
 
-        const int64_t obase = a.out.base[s], ocap = a.out.cap[s];
-        const int64_t g0 = a.ws.stg_start[L.h.sl];
-        const int64_t gcap = a.ws.stg_start[L.h.sl + 1] - g0;
+        if (pend) {
+            TileLds<WG, ITEMS> &P = L[cur ^ 1];
+            walk_back<WG, ITEMS>(a, P);
+            __syncthreads();
+            scatter_stash<WG, ITEMS, FT>(a, P, S, fl);
+        }
+
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            if (d[k] == 0xff)
-                continue;
-            const int b = d[k];
-            const int e = k * NW + w;
-            if (b == PM_STAY) {
-                const int64_t slot = (int64_t)L.base[0] + L.cnt[0][e] + rank[k];
-                if (slot < ocap)
-                    put_record<FT>(a.out, obase + slot, X[k], V[k], tau[k], id[k]);
-                else
-                    fl |= PM_F_DEST_OVERFLOW;
-            } else {
-                const int64_t m = (int64_t)L.base[1] + L.cnt[1][e] + rank[k];
-                if (m < gcap) {
-                    double Xs[3];
+            const int i = k * WG + tid;
+            uint32_t code = 0xffu;
+            if (d[k] != 0xff) {
+                const int b = d[k];
+                const int e = k * NW + w;
+                if (b == PM_STAY) {
+                    code = ((C.cnt[0][e] + rank[k]) << 8) | (uint32_t)b;
+                } else {
+                    code = ((C.cnt[1][e] + rank[k]) << 8) | (uint32_t)b;
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        Xs[c] = shifted(a.dc, c, own[c], dir_o(b, c), X[k][c]);
-                    put_staged<FT>(a.ws, g0 + m, Xs, V[k], tau[k], id[k], b);
-                } else {
-                    fl |= PM_F_SEND_OVERFLOW;
+                        X[k][c] = shifted(a.dc, c, own[c], dir_o(b, c), X[k][c]);
                 }
             }
+            S.code[i] = code;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                S.x[c][i] = X[k][c];
+                S.v[c][i] = V[k][c];
+            }
+            S.tau[i] = tau[k];
+            S.id[i] = id[k];
         }
-        publish_counts<WG, ITEMS>(a, L);
+        pend = true;
+        cur ^= 1;
         __syncthreads();
+    }
+    if (pend) {
+        TileLds<WG, ITEMS> &P = L[cur ^ 1];
+        walk_back<WG, ITEMS>(a, P);
+        __syncthreads();
+        scatter_stash<WG, ITEMS, FT>(a, P, S, fl);
     }
     if (fl)
         flag_or(hdr, fl);
