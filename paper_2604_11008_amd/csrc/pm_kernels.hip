@@ -141,8 +141,23 @@ __device__ __forceinline__ void stencil_index(const DField &f, const double X[3]
         fr[a] = (FT)axis_corner<HALO>(f, a, X[a], c0[a], fl);
 }
 
+// Two x-adjacent node values in one vector load (16 bytes for double, 8 for
+// float).  The address is only FT-aligned, which global loads accept.
+template <typename FT>
+__device__ __forceinline__ void load_pair(const FT *p, FT &lo, FT &hi)
+{
+    struct Pair {
+        FT a, b;
+    } q;
+    __builtin_memcpy(&q, p, sizeof q);
+    lo = q.a;
+    hi = q.b;
+}
+
 // The 24 node values of a stencil: v[c][2*r + x] for component c, row r
-// (y and z corner: 00, 10, 01, 11) and x corner x.
+// (y and z corner: 00, 10, 01, 11) and x corner x.  Each row's x pair is one
+// load; where a periodic field wraps (x corner n-1, then 0) the pair starts
+// one node earlier and the node at 0 is loaded on its own (n >= 2).
 template <typename FT, bool HALO>
 __device__ __forceinline__ void stencil_load(const DField &f, const int c0[3], FT v[3][8])
 {
@@ -153,13 +168,24 @@ __device__ __forceinline__ void stencil_load(const DField &f, const int c0[3], F
                           f.sx * (int64_t)cy1 + f.sxy * (int64_t)c0[2],
                           f.sx * (int64_t)c0[1] + f.sxy * (int64_t)cz1,
                           f.sx * (int64_t)cy1 + f.sxy * (int64_t)cz1};
+    const bool wrap = !HALO && cx1 != c0[0] + 1;
+    const int xa = wrap ? c0[0] - 1 : c0[0];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const FT *u = (const FT *)f.u[c];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            v[c][2 * k] = u[r[k] + c0[0]];
-            v[c][2 * k + 1] = u[r[k] + cx1];
+        for (int k = 0; k < 4; ++k)
+            load_pair<FT>(u + r[k] + xa, v[c][2 * k], v[c][2 * k + 1]);
+    }
+    if (wrap) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const FT *u = (const FT *)f.u[c];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[c][2 * k] = v[c][2 * k + 1];
+                v[c][2 * k + 1] = u[r[k] + cx1];
+            }
         }
     }
 }
