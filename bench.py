@@ -196,6 +196,11 @@ def main():
     alg = accounting.step_algorithmic_bytes(npart, migrants, touched,
                                             "mixed" if mixed else "f64")
 
+    # the state the timed steps start from, so the graph replays below start
+    # from it too (kernel time drifts as particles disperse from their sorted
+    # start order)
+    snap = [t.clone() for t in (pa.x, pa.v, pa.tau, pa.id, pa.count)]
+
     # timed region
     if not args.graph:
         ctx.set_timing(args.steps)
@@ -232,6 +237,7 @@ def main():
                 "frac": round(achieved / accounting.HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": "k_step (fused interpolate/advance/classify/scan/scatter)",
                 "kernel_ms": round(k_ms, 5),
+                "kernel_ms_first_last": [round(k_each[0], 5), round(k_each[-1], 5)],
                 "algorithmic_bytes_per_launch": alg["fused_kernel"]}
 
     extra = {}
@@ -239,6 +245,10 @@ def main():
         # the same steps replayed from captured HIP graphs (two graphs: A->B, B->A)
         ctx.set_timing(0)
         ctx.set_graph(True)
+        if pa.size != snap[0].shape[1]:
+            raise SystemExit("pool size changed")
+        for t, v in zip((pa.x, pa.v, pa.tau, pa.id, pa.count), snap):
+            t.copy_(v)
         for _ in range(2):
             ctx.step(field, dc, pa, pb, send, params)
             pa, pb = pb, pa

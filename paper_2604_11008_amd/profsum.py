@@ -10,6 +10,7 @@ longer applies and bench.py reports traffic as null.
 
 Usage (after the rocprofv3 runs):
   python -m paper_2604_11008_amd.profsum stats  <kernel_stats.csv>
+  python -m paper_2604_11008_amd.profsum trace  <kernel_trace.csv> <kernel substring> <skip> <count>
   python -m paper_2604_11008_amd.profsum counters <counter_collection.csv>
   python -m paper_2604_11008_amd.profsum traffic <fetch.csv> <write.csv> <kernel substring> <out.json>
 """
@@ -58,6 +59,16 @@ def stats(path, top=12):
         tot = float(_get(r, "TotalDurationNs", "TOTAL_DURATION_NS")) / 1e3
         out.append((name, calls, avg, tot))
     return out
+
+
+def trace_window(path, substr, skip, count):
+    """Durations (us) of the dispatches skip .. skip+count-1, in start order,
+    of the kernels whose name contains substr (kernel_trace.csv)."""
+    rows = [r for r in _rows(path) if substr in _get(r, "Kernel_Name", "KERNEL_NAME")]
+    rows.sort(key=lambda r: int(_get(r, "Start_Timestamp", "START_TIMESTAMP")))
+    d = [(int(_get(r, "End_Timestamp", "END_TIMESTAMP")) -
+          int(_get(r, "Start_Timestamp", "START_TIMESTAMP"))) / 1e3 for r in rows]
+    return d[skip:skip + count], len(d)
 
 
 def counter_means(path):
@@ -121,6 +132,11 @@ def main(argv):
     if argv[0] == "stats":
         for name, calls, avg, tot in stats(argv[1]):
             print(f"{avg:12.2f} us avg {calls:6d} calls {tot:12.1f} us total  {name[:100]}")
+    elif argv[0] == "trace":
+        d, n = trace_window(argv[1], argv[2], int(argv[3]), int(argv[4]))
+        print(f"{argv[2]}: dispatches {argv[3]}..{int(argv[3]) + len(d) - 1} of {n}: "
+              f"mean {sum(d) / len(d):.2f} us, min {min(d):.2f}, max {max(d):.2f}, "
+              f"first {d[0]:.2f}, last {d[-1]:.2f}")
     elif argv[0] == "counters":
         for k, d in counter_means(argv[1]).items():
             for c, (v, n) in sorted(d.items()):
