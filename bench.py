@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="auto", choices=["auto", "f64", "mixed"],
+                    help="override the workload's arithmetic (mixed: float32 field, "
+                         "velocities and tau; float64 positions)")
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
     ap.add_argument("--tune", default=None, help="wg,items[,blocks_per_cu] or 'auto'")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
@@ -151,7 +154,12 @@ def main():
     wl = gen.make_workload(args.config, field_backend="device" if big else "numpy",
                            slack=0.25 if multi else 0.05, extra=4096 if multi else 1024)
     t_gen = time.perf_counter() - t_gen
-    mixed = wl.mode == "mixed"
+    mixed = wl.mode == "mixed" if args.precision == "auto" else args.precision == "mixed"
+    if mixed != (wl.mode == "mixed"):
+        cast = np.float32 if mixed else np.float64
+        wl.pool.v = wl.pool.v.astype(cast)
+        wl.pool.tau = wl.pool.tau.astype(cast)
+        wl.mode = "mixed" if mixed else "f64"
     fdt = np.float32 if mixed else np.float64
     field = pm.DeviceField(wl.stored_field(fdt), wl.n, wl.halo, wl.L, device=dev)
     dc = pm.Decomp(wl.p, wl.bounds)
@@ -342,7 +350,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "mixed-f32/f64" if mixed else "f64", "data": "synthetic",
-        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}",
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}" +
+                   (f" (run at {args.precision})" if args.precision != "auto" else ""),
                    "particles": npart, "grid": wl.n, "halo": wl.halo,
                    "subdomains": list(wl.p), "graph": bool(args.graph),
                    "tuning": list(ctx.get_tuning())},

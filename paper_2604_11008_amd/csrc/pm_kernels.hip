@@ -551,11 +551,11 @@ __device__ __forceinline__ void put_record(const DPool &P, int64_t at, const dou
 {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        P.x[c][at] = X[c];
-        ((FT *)P.v[c])[at] = V[c];
+        __builtin_nontemporal_store(X[c], &P.x[c][at]);
+        __builtin_nontemporal_store(V[c], &((FT *)P.v[c])[at]);
     }
-    ((FT *)P.tau)[at] = tau;
-    P.id[at] = id;
+    __builtin_nontemporal_store(tau, &((FT *)P.tau)[at]);
+    __builtin_nontemporal_store(id, &P.id[at]);
 }
 
 template <typename FT>
@@ -840,18 +840,20 @@ __global__ __launch_bounds__(WG) void k_step(const KArgs a)
         int d[ITEMS];
         uint32_t rank[ITEMS];
         // records past the end of a ragged tile repeat the tile's last one and
-        // are dropped after classification, so no lane branches here
+        // are dropped after classification, so no lane branches here; the
+        // record streams are read once and written once, so they are loaded
+        // and stored non-temporally to leave the L2 to the field
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const int i = k * WG + tid;
             const int64_t p = first + (i < nitems ? i : nitems - 1);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                X[k][c] = a.in.x[c][p];
-                V[k][c] = ((const FT *)a.in.v[c])[p];
+                X[k][c] = __builtin_nontemporal_load(&a.in.x[c][p]);
+                V[k][c] = __builtin_nontemporal_load(&((const FT *)a.in.v[c])[p]);
             }
-            tau[k] = ((const FT *)a.in.tau)[p];
-            id[k] = a.in.id[p];
+            tau[k] = __builtin_nontemporal_load(&((const FT *)a.in.tau)[p]);
+            id[k] = __builtin_nontemporal_load(&a.in.id[p]);
         }
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {

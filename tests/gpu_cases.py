@@ -40,7 +40,8 @@ class Case:
             wl.pool.v = U.astype(np.float32)
             wl.pool.tau = wl.pool.tau.astype(np.float32)
         else:
-            wl.pool.v[:] = U
+            wl.pool.v = U.astype(np.float64)
+            wl.pool.tau = wl.pool.tau.astype(np.float64)
         self.host = wl.pool
         self.dev = torch.device("cuda:0")
         fdev = [np.asarray(u, dtype=np.float32) for u in self.fh] if self.mode == "mixed" \
