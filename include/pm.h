@@ -10,11 +10,12 @@
  *   3. the boundary-crossing check against the owner subdomain, generalised
  *      from the paper's send/stay mask to 26 neighbour directions
  *      (Sect. 2.3.3, stage 1);
- *   4. a prefix scan of the 27 direction masks giving every particle a unique
- *      slot (Sect. 2.3.3, stages 2-3: scan[i] = sum of mask[1..i]), packing
- *      the leavers into per-direction send buffers and compacting the
- *      stayers, then appending what every subdomain receives (unpacking,
- *      Sect. 3.2.2).
+ *   4. a prefix scan of the send/stay mask giving every particle a unique
+ *      slot (Sect. 2.3.3, stages 2-3: scan[i] = sum of mask[1..i]); the
+ *      leavers' slots are then split by direction, which yields exactly the
+ *      slots of per-direction counters; packing the leavers into
+ *      per-direction send buffers and compacting the stayers, then appending
+ *      what every subdomain receives (unpacking, Sect. 3.2.2).
  * The subdomains are virtual partitions of one device's memory, so the
  * exchange between them is an on-device copy.
  *

@@ -1,0 +1,57 @@
+"""Sector footprint of the fused kernel's stencil gathers on the 256^3
+single-subdomain workload (run by hand: python tests/footprint.py).
+
+For groups of G consecutive records in pool order (G = 64: one wave's records
+at a time; 256: one item of a 256x4 tile; 1024: a whole tile), counts the
+distinct 64-byte sectors of each field component that the group's stage-1 and
+stage-2 stencils touch, and prints the sum over groups x 3 components x 64 B:
+the field bytes a cache that kept exactly one group's data would fetch.  The
+stage-2 position is X + dt U(X) with U from the oracle (the step starts from
+V = U(X)).  Compare with the measured FETCH_SIZE of the kernel.
+"""
+import os
+import sys
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import oracle  # noqa: E402
+from paper_2604_11008_amd import gen  # noqa: E402
+
+
+def sectors(X, n, L, halo):
+    S = n + 2 * halo
+    s = X * (n / L) - 0.5
+    i = np.floor(s).astype(np.int64) + halo
+    out = []
+    for dy in (0, 1):
+        for dz in (0, 1):
+            row = (i[1] + dy) + S * (i[2] + dz)
+            b0 = (row * S + i[0]) * 8
+            out.append(b0 // 64)
+            out.append((b0 + 15) // 64)
+    return np.stack(out)
+
+
+def main():
+    wl = gen.make_workload("C2")
+    n, L = wl.n, wl.L
+    x = wl.pool.x[:, :int(wl.pool.count[0])]
+    of = oracle.Field(wl.stored_field(np.float64), n, wl.halo, L)
+    U, _ = oracle.interp(of, x)
+    xs = x + wl.dt * U
+    s1, s2 = sectors(x, n, L, wl.halo), sectors(xs, n, L, wl.halo)
+    np_ = x.shape[1]
+    for G in (64, 128, 256, 512, 1024, 2048, 4096):
+        tot = 0
+        for g0 in range(0, np_, G):
+            tot += np.unique(np.concatenate([s1[:, g0:g0 + G].ravel(),
+                                             s2[:, g0:g0 + G].ravel()])).size
+        print(f"groups of {G:5d}: {tot * 3 * 64 / 1e9:.3f} GB "
+              f"({tot * 3 * 64 / np_:.1f} B/particle)")
+    allu = np.unique(np.concatenate([s1.ravel(), s2.ravel()])).size
+    print(f"whole step: {allu * 3 * 64 / 1e9:.3f} GB ({allu * 3 * 64 / np_:.1f} B/particle)")
+
+
+if __name__ == "__main__":
+    main()
