@@ -79,7 +79,16 @@ class _Pool(C.Structure):
 
 
 class _Params(C.Structure):
-    _fields_ = [("dt", C.c_double), ("g", C.c_double * 3)]
+    _fields_ = [("dt", C.c_double), ("g", C.c_double * 3), ("drag", C.c_int),
+                ("nu", C.c_double), ("density_ratio", C.c_double)]
+
+
+DRAG = {"stokes": 0, "nonlinear": 1}
+
+
+def _params(dt, g, drag, nu, density_ratio):
+    return _Params(float(dt), (C.c_double * 3)(*g), DRAG[drag], float(nu),
+                   float(density_ratio))
 
 
 def _ptr(a):
@@ -167,12 +176,15 @@ def interp(field: Field, X):
     return U, int(flags)
 
 
-def advance(field: Field, x, v, tau, dt, g=(0.0, 0.0, 0.0)):
-    """One Heun step; returns new (x, v, flags), inputs untouched."""
+def advance(field: Field, x, v, tau, dt, g=(0.0, 0.0, 0.0), drag="stokes", nu=1.5e-5,
+            density_ratio=843.0):
+    """One Heun step; returns new (x, v, flags), inputs untouched.  drag is
+    "stokes" (f = 1) or "nonlinear" (f = 1 + 0.15 Re_p^0.687, with nu and
+    rho_p/rho)."""
     x = np.array(x, dtype=np.float64, order="C", copy=True)
     v = np.array(v, dtype=np.float64, order="C", copy=True)
     tau = _f64(tau)
-    pr = _Params(float(dt), (C.c_double * 3)(*g))
+    pr = _params(dt, g, drag, nu, density_ratio)
     xp = (C.c_void_p * 3)(*[x[a].ctypes.data for a in range(3)])
     vp = (C.c_void_p * 3)(*[v[a].ctypes.data for a in range(3)])
     flags = lib().orc_advance(field.ref, C.byref(pr), x.shape[1], xp, vp, _ptr(tau))
@@ -220,11 +232,12 @@ def append(decomp: Decomp, send, stay_count, pout):
     return int(flags)
 
 
-def step(field: Field, decomp: Decomp, dt, g, pin, pout, send):
+def step(field: Field, decomp: Decomp, dt, g, pin, pout, send, drag="stokes", nu=1.5e-5,
+         density_ratio=843.0):
     """Whole step pin -> pout (pin unchanged).  Returns (stay_count, flags)."""
     vin, vout, vsend = _PoolView(pin), _PoolView(pout), _PoolView(send)
     stay = np.zeros(len(vin.base), dtype=np.int64)
-    pr = _Params(float(dt), (C.c_double * 3)(*g))
+    pr = _params(dt, g, drag, nu, density_ratio)
     flags = lib().orc_step(field.ref, decomp.ref, C.byref(pr), vin.ref, vout.ref,
                            vsend.ref, _ptr(stay))
     vout.write_back()

@@ -137,10 +137,23 @@ unsigned orc_interp_many(const orc_field *f, int64_t n, const double *x,
 
 /* ------------------------------------------------------------------ */
 /* Particle ODE, two-stage second-order RK (Heun), Sect. 2.2.           */
-/*   A = (U(X) - V)/tau + g                                             */
+/*   A = f (U(X) - V)/tau + g                                           */
 /*   X* = X + dt V,            V* = V + dt A(X, V)                      */
 /*   X' = X + dt/2 (V + V*),   V' = V + dt/2 (A(X, V) + A(X*, V*))      */
 /* ------------------------------------------------------------------ */
+
+/* Drag factor f of a particle with relaxation time t and slip U - V
+ * (Sect. 2.2): 1 for Stokes drag; else r from t = (2/9)(rho_p/rho) r^2/nu,
+ * Re_p = 2 r |V - U| / nu and f = 1 + 0.15 Re_p^0.687. */
+static double drag_factor(const orc_params *pr, double t, const double slip[3])
+{
+    if (pr->drag != ORC_DRAG_NONLINEAR)
+        return 1.0;
+    const double r = sqrt(9.0 * pr->nu * t / (2.0 * pr->density_ratio));
+    const double w = sqrt(slip[0] * slip[0] + slip[1] * slip[1] + slip[2] * slip[2]);
+    const double re = 2.0 * r * w / pr->nu;
+    return 1.0 + 0.15 * pow(re, 0.687);
+}
 
 unsigned orc_advance(const orc_field *f, const orc_params *pr, int64_t n,
                      double *x[3], double *v[3], const double *tau)
@@ -150,7 +163,7 @@ unsigned orc_advance(const orc_field *f, const orc_params *pr, int64_t n,
     const double half_dt = 0.5 * dt;
 
     for (int64_t p = 0; p < n; ++p) {
-        double X[3], V[3], U1[3], A1[3], Xs[3], Vs[3], U2[3], A2[3];
+        double X[3], V[3], U1[3], A1[3], Xs[3], Vs[3], U2[3], A2[3], s1[3], s2[3];
         const double t = tau[p];
 
         for (int a = 0; a < 3; ++a) {
@@ -158,14 +171,20 @@ unsigned orc_advance(const orc_field *f, const orc_params *pr, int64_t n,
             V[a] = v[a][p];
         }
         flags |= orc_interp(f, X, U1);
+        for (int a = 0; a < 3; ++a)
+            s1[a] = U1[a] - V[a];
+        const double f1 = drag_factor(pr, t, s1);
         for (int a = 0; a < 3; ++a) {
-            A1[a] = (U1[a] - V[a]) / t + pr->g[a];
+            A1[a] = f1 * s1[a] / t + pr->g[a];
             Xs[a] = X[a] + dt * V[a];
             Vs[a] = V[a] + dt * A1[a];
         }
         flags |= orc_interp(f, Xs, U2);
+        for (int a = 0; a < 3; ++a)
+            s2[a] = U2[a] - Vs[a];
+        const double f2 = drag_factor(pr, t, s2);
         for (int a = 0; a < 3; ++a) {
-            A2[a] = (U2[a] - Vs[a]) / t + pr->g[a];
+            A2[a] = f2 * s2[a] / t + pr->g[a];
             x[a][p] = X[a] + half_dt * (V[a] + Vs[a]);
             v[a][p] = V[a] + half_dt * (A1[a] + A2[a]);
         }

@@ -10,9 +10,12 @@
  * What it computes (LCS.jl, arXiv 2604.11008):
  *   - trilinear interpolation of the fluid velocity from the eight
  *     surrounding cell-centre values (Sect. 2.2, Particle Phase);
- *   - the particle ODE dX/dt = V, dV/dt = -(f/tau)(V - U(X)) with f = 1
- *     (Stokes drag) plus a constant body force g, advanced by a two-stage
- *     second-order Runge-Kutta method, read as Heun's method (Sect. 2.2);
+ *   - the particle ODE dX/dt = V, dV/dt = -(f/tau)(V - U(X)) plus a
+ *     constant body force g, advanced by a two-stage second-order
+ *     Runge-Kutta method, read as Heun's method (Sect. 2.2); the drag factor
+ *     is f = 1 (Stokes drag) or the paper's nonlinear correction
+ *     f = 1 + 0.15 Re_p^0.687, Re_p = 2r|V - U(X)|/nu, with the radius r
+ *     from tau = (2/9)(rho_p/rho)(r^2/nu) (Sect. 2.2);
  *   - the boundary-crossing check of each particle against its subdomain
  *     (Sect. 2.3.3, stage 1, "mask"), generalised to the 26 neighbours;
  *   - the sequential per-direction-counter partition of the original
@@ -76,10 +79,19 @@ typedef struct {
     uint64_t *id;
 } orc_pool;
 
-/* Step parameters: time step and constant body force (gravity). */
+/* Drag laws. */
+#define ORC_DRAG_STOKES    0  /* f = 1                                        */
+#define ORC_DRAG_NONLINEAR 1  /* f = 1 + 0.15 Re_p^0.687 (Sect. 2.2)          */
+
+/* Step parameters: time step, constant body force (gravity), drag law, and
+ * for the nonlinear law the kinematic viscosity nu and the particle-to-fluid
+ * density ratio rho_p/rho (in the units of the field, box and tau). */
 typedef struct {
     double dt;
     double g[3];
+    int drag;
+    double nu;
+    double density_ratio;
 } orc_params;
 
 /* U(X) by trilinear interpolation.  Returns error bits (ORC_HALO). */
