@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--precision", default="auto", choices=["auto", "f64", "mixed"],
                     help="override the workload's arithmetic (mixed: float32 field, "
                          "velocities and tau; float64 positions)")
+    ap.add_argument("--drag", default="stokes", choices=["stokes", "nonlinear"],
+                    help="drag law: Stokes (f = 1) or the paper's nonlinear correction "
+                         "(nu = 1.5e-5, rho_p/rho = 843 in the field's units)")
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
     ap.add_argument("--tune", default=None, help="wg,items[,blocks_per_cu] or 'auto'")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
@@ -70,7 +73,7 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(wl, seconds):
+def cpu_baseline(wl, seconds, drag="stokes"):
     """The oracle, single-threaded, on whole steps of the same workload."""
     import oracle
     pool = wl.pool
@@ -84,7 +87,7 @@ def cpu_baseline(wl, seconds):
     while True:
         out = gen.empty_pool(pool.base, pool.cap)
         send = gen.empty_pool(sb, sc)
-        oracle.step(of, od, wl.dt, wl.g, pool, out, send)
+        oracle.step(of, od, wl.dt, wl.g, pool, out, send, drag=drag)
         steps += 1
         done += npart
         if time.perf_counter() - t0 >= seconds or steps >= 8:
@@ -174,7 +177,7 @@ def main():
     ctx = pm.Context(size, send.size, dc.nsub, device=dev)
     # v0 = U(x0), interpolated on the device
     pa.v.copy_(ctx.interp(field, pa.x))
-    params = pm.Params(wl.dt, wl.g)
+    params = pm.Params(wl.dt, wl.g, drag=args.drag)
     if args.tune == "auto":
         ctx.autotune(field, dc, pa, pb, send, params, cache_path=args.tune_cache)
     elif args.tune:
@@ -331,7 +334,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(wl, args.cpu_seconds)
+        cpu = cpu_baseline(wl, args.cpu_seconds, args.drag)
         # the paper's CPU-delegated estimate (Sect. 3.2.2) for this host and workload:
         # arrays out and back over the link, packed and unpacked at one core's bandwidth
         h2d, d2h = link_gbps(torch, dev)
@@ -351,7 +354,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "mixed-f32/f64" if mixed else "f64", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}" +
-                   (f" (run at {args.precision})" if args.precision != "auto" else ""),
+                   (f" (run at {args.precision})" if args.precision != "auto" else "") +
+                   (", nonlinear drag" if args.drag == "nonlinear" else ""),
                    "particles": npart, "grid": wl.n, "halo": wl.halo,
                    "subdomains": list(wl.p), "graph": bool(args.graph),
                    "tuning": list(ctx.get_tuning())},

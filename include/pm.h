@@ -5,8 +5,9 @@
  * every particle of a pool partitioned into subdomains:
  *   1. U(X): trilinear interpolation of the fluid velocity from the eight
  *      surrounding cell-centre values (Sect. 2.2, Particle Phase);
- *   2. dX/dt = V, dV/dt = -(1/tau)(V - U(X)) + g, advanced with a two-stage
- *      second-order Runge-Kutta method (Heun) (Sect. 2.2; drag factor f = 1);
+ *   2. dX/dt = V, dV/dt = -(f/tau)(V - U(X)) + g, advanced with a two-stage
+ *      second-order Runge-Kutta method (Heun) (Sect. 2.2), with the drag
+ *      factor f = 1 (Stokes) or the paper's nonlinear correction (pm_drag);
  *   3. the boundary-crossing check against the owner subdomain, generalised
  *      from the paper's send/stay mask to 26 neighbour directions
  *      (Sect. 2.3.3, stage 1);
@@ -143,17 +144,36 @@ typedef struct {
     uint64_t *id;
 } pm_sendbufs;
 
-/* Time step and constant body force (gravity) added to dV/dt. */
+/* Drag laws of the particle ODE dV/dt = -(f/tau)(V - U(X)) + g (Sect. 2.2). */
+typedef enum {
+    PM_DRAG_STOKES = 0,    /* f = 1                                            */
+    PM_DRAG_NONLINEAR = 1  /* f = 1 + 0.15 Re_p^0.687, Re_p = 2 r |V - U| / nu,
+                              r from tau = (2/9)(rho_p/rho) r^2 / nu           */
+} pm_drag;
+
+/* Time step, constant body force (gravity) added to dV/dt, and the drag law.
+ * nu (kinematic viscosity) and density_ratio (rho_p/rho) are read only for
+ * PM_DRAG_NONLINEAR, in the units of the field, the box and tau; both must
+ * then be positive and finite. */
 typedef struct {
     double dt;
     double g[3];
+    int32_t drag;          /* pm_drag */
+    int32_t pad_;
+    double nu;
+    double density_ratio;
 } pm_params;
 
 /* Launch shape of the tile kernels: workgroup size (256 or 512), records
- * per thread (1, 2, 4 or 8); tile = wg*items records.  blocks_per_cu is the
- * persistent grid's workgroups per compute unit: 0 = the runtime's occupancy
- * estimate; an explicit 1..32 may exceed it (surplus workgroups start as
- * others retire; tiles are claimed by ticket, so this cannot deadlock). */
+ * per thread (1, 2, 4 or 8); tile = wg*items records.  wg = 0 in
+ * pm_set_tuning selects the per-variant defaults (256 x 4; 256 x 2 for FP64
+ * periodic fields with the nonlinear drag law), which a context uses until
+ * pm_set_tuning or pm_autotune fixes a shape; pm_get_tuning then reports the
+ * shape of the last launch.  blocks_per_cu is the persistent grid's
+ * workgroups per compute unit: 0 = the runtime's occupancy estimate; an
+ * explicit 1..32 may exceed it (surplus workgroups start as others retire;
+ * tiles are claimed by ticket, so this cannot deadlock).  No shape changes
+ * any result. */
 typedef struct {
     int32_t wg;
     int32_t items;

@@ -93,6 +93,8 @@ struct pm_ctx {
     pm::DWS ws{};
     int32_t nsub_max = 0;
     pm::Shape shape{256, 4};
+    bool shape_auto = true;         // no pm_set_tuning / pm_autotune yet
+    pm::Shape last_shape{256, 4};   // the shape of the last launch
     int blocks_per_cu = 0;
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
@@ -224,6 +226,17 @@ pm_status conv_params(const pm_params *pr, pm::KArgs &k)
     if (!std::isfinite(pr->dt) || !std::isfinite(pr->g[0]) || !std::isfinite(pr->g[1]) ||
         !std::isfinite(pr->g[2]))
         return arg_error("params must be finite");
+    if (pr->drag != PM_DRAG_STOKES && pr->drag != PM_DRAG_NONLINEAR)
+        return arg_error("params.drag = %d is not a pm_drag", pr->drag);
+    if (pr->drag == PM_DRAG_NONLINEAR &&
+        !(std::isfinite(pr->nu) && pr->nu > 0 && std::isfinite(pr->density_ratio) &&
+          pr->density_ratio > 0))
+        return arg_error("nonlinear drag needs positive finite nu and density_ratio");
+    k.drag = pr->drag;
+    // Re_p = 2 r |V - U| / nu with r^2 = 9 nu tau / (2 rho_p/rho), i.e.
+    // Re_p = sqrt(18 tau / (rho_p/rho nu)) |V - U|
+    k.kappa = pr->drag == PM_DRAG_NONLINEAR ? std::sqrt(18.0 / (pr->density_ratio * pr->nu)) : 0.0;
+    k.kappaf = (float)k.kappa;
     k.dt = pr->dt;
     k.half_dt = 0.5 * pr->dt;
     k.dtf = (float)pr->dt;
@@ -244,14 +257,26 @@ pm_status check_range(pm_ctx *ctx, int32_t nsub, int32_t first, int32_t count)
     return PM_OK;
 }
 
-int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed, bool halo)
+// Launch shape of a call: the tuned one, else a measured default — 256
+// threads x 4 records, except the FP64 periodic kernels with the nonlinear
+// drag law, whose 4-record variant runs out of registers (x 2 records).
+pm::Shape shape_for(pm_ctx *ctx, bool mixed, bool halo, bool nonlinear)
+{
+    pm::Shape sh = ctx->shape;
+    if (ctx->shape_auto)
+        sh = (!mixed && !halo && nonlinear) ? pm::Shape{256, 2} : pm::Shape{256, 4};
+    ctx->last_shape = sh;
+    return sh;
+}
+
+int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed, bool halo, bool nonlinear)
 {
     // An explicit figure may exceed the runtime's occupancy estimate: workgroups
     // that do not fit start as others retire, and since tiles are claimed by
     // ticket when a workgroup runs, no running workgroup waits on one that has
     // not started.
     const int per = ctx->blocks_per_cu > 0 ? ctx->blocks_per_cu
-                                           : pm::step_occupancy(sh, mixed, halo);
+                                           : pm::step_occupancy(sh, mixed, halo, nonlinear);
     return std::max(1, ctx->cus * per);
 }
 
@@ -260,7 +285,8 @@ int append_cpt(int32_t count) { return std::max(1, 2048 / std::max(1, count)); }
 // Queue the fused step (prep, fused kernel, exchange) on `st`.
 pm_status queue_step(pm_ctx *ctx, pm::KArgs &k, bool mixed, hipStream_t st, bool timed)
 {
-    k.tile = ctx->shape.wg * ctx->shape.items;
+    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0);
+    k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(k.sub_count);
     PM_HIP(pm::launch_prep(k,
                            pm::kPrepTiles | pm::kPrepStaging | pm::kPrepZeroLb |
@@ -270,7 +296,7 @@ pm_status queue_step(pm_ctx *ctx, pm::KArgs &k, bool mixed, hipStream_t st, bool
            "prep launch");
     if (timed)
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount], st), "event record");
-    PM_HIP(pm::launch_step(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed, k.f.halo != 0), st),
+    PM_HIP(pm::launch_step(k, sh, mixed, persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0), st),
            "fused step launch");
     if (timed) {
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount + 1], st), "event record");
@@ -421,9 +447,10 @@ pm_status pm_interp_advance(pm_ctx *ctx, const pm_field *field, pm_particles *in
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = sub_first;
     k.sub_count = sub_count;
-    k.tile = ctx->shape.wg * ctx->shape.items;
+    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0);
+    k.tile = sh.wg * sh.items;
     PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn, st), "prep launch");
-    PM_HIP(pm::launch_advance(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed, k.f.halo != 0), st),
+    PM_HIP(pm::launch_advance(k, sh, mixed, persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0), st),
            "advance launch");
     return PM_OK;
 }
@@ -457,13 +484,14 @@ pm_status pm_classify_scan_pack(pm_ctx *ctx, const pm_decomp *decomp, const pm_p
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = sub_first;
     k.sub_count = sub_count;
-    k.tile = ctx->shape.wg * ctx->shape.items;
+    const pm::Shape sh = shape_for(ctx, mixed, false, false);
+    k.tile = sh.wg * sh.items;
     PM_HIP(pm::launch_prep(k,
                            pm::kPrepTiles | pm::kPrepStaging | pm::kPrepZeroLb |
                                pm::kPrepZeroCounts | pm::kPrepCheckIn | pm::kPrepCheckSend,
                            st),
            "prep launch");
-    PM_HIP(pm::launch_classify(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed, k.f.halo != 0), st),
+    PM_HIP(pm::launch_classify(k, sh, mixed, persistent_grid(ctx, sh, mixed, false, false), st),
            "classify launch");
     PM_HIP(pm::launch_route(k, mixed, false, st), "route launch");
     return PM_OK;
@@ -499,13 +527,14 @@ pm_status pm_compact_append(pm_ctx *ctx, const pm_decomp *decomp, const pm_parti
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = sub_first;
     k.sub_count = sub_count;
-    k.tile = ctx->shape.wg * ctx->shape.items;
+    const pm::Shape sh = shape_for(ctx, mixed, false, false);
+    k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(sub_count);
     PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn | pm::kPrepCheckOut |
                                   pm::kPrepCheckSend,
                            st),
            "prep launch");
-    PM_HIP(pm::launch_compact(k, ctx->shape, mixed, persistent_grid(ctx, ctx->shape, mixed, k.f.halo != 0), st),
+    PM_HIP(pm::launch_compact(k, sh, mixed, persistent_grid(ctx, sh, mixed, false, false), st),
            "compact launch");
     const int grid = std::min(4096, sub_count * k.cpt);
     PM_HIP(pm::launch_append(k, mixed, std::max(1, grid), st), "append launch");
@@ -558,12 +587,13 @@ pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
         return queue_step(ctx, k, mixed, st, timed);
     }
     // graph path: one captured graph per distinct argument set and shape
-    k.tile = ctx->shape.wg * ctx->shape.items;
+    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0);
+    k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(k.sub_count);
-    std::vector<unsigned char> key(sizeof k + sizeof ctx->shape + sizeof(int));
+    std::vector<unsigned char> key(sizeof k + sizeof sh + sizeof(int));
     std::memcpy(key.data(), &k, sizeof k);
-    std::memcpy(key.data() + sizeof k, &ctx->shape, sizeof ctx->shape);
-    std::memcpy(key.data() + sizeof k + sizeof ctx->shape, &ctx->blocks_per_cu, sizeof(int));
+    std::memcpy(key.data() + sizeof k, &sh, sizeof sh);
+    std::memcpy(key.data() + sizeof k + sizeof sh, &ctx->blocks_per_cu, sizeof(int));
     for (auto &g : ctx->graphs)
         if (g.key == key) {
             PM_HIP(hipGraphLaunch(g.exec, st), "graph launch");
@@ -614,12 +644,18 @@ pm_status pm_set_tuning(pm_ctx *ctx, const pm_tuning *t)
 {
     if (!ctx || !t)
         return arg_error("NULL argument");
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 32)
+        return arg_error("blocks_per_cu out of range");
+    if (t->wg == 0) {  // back to the per-variant defaults
+        ctx->shape_auto = true;
+        ctx->blocks_per_cu = t->blocks_per_cu;
+        return PM_OK;
+    }
     const pm::Shape sh{t->wg, t->items};
     if (!pm::shape_supported(sh))
         return arg_error("launch shape wg=%d items=%d is not built", t->wg, t->items);
-    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 32)
-        return arg_error("blocks_per_cu out of range");
     ctx->shape = sh;
+    ctx->shape_auto = false;
     ctx->blocks_per_cu = t->blocks_per_cu;
     return PM_OK;
 }
@@ -628,8 +664,9 @@ pm_status pm_get_tuning(pm_ctx *ctx, pm_tuning *t)
 {
     if (!ctx || !t)
         return arg_error("NULL argument");
-    t->wg = ctx->shape.wg;
-    t->items = ctx->shape.items;
+    const pm::Shape sh = ctx->shape_auto ? ctx->last_shape : ctx->shape;
+    t->wg = sh.wg;
+    t->items = sh.items;
     t->blocks_per_cu = ctx->blocks_per_cu;
     t->pad_ = 0;
     return PM_OK;
@@ -712,6 +749,7 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
             fclose(fp);
             if (hit && pm::shape_supported({wg, items})) {
                 ctx->shape = {wg, items};
+                ctx->shape_auto = false;
                 ctx->blocks_per_cu = bpc;
                 return PM_OK;
             }
@@ -728,8 +766,9 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
     PM_HIP(hipEventCreate(&e0), "event create");
     PM_HIP(hipEventCreate(&e1), "event create");
     float best = 1e30f;
-    pm::Shape best_sh = ctx->shape;
+    pm::Shape best_sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0);
     int best_bpc = ctx->blocks_per_cu;
+    ctx->shape_auto = false;  // the sweep sets the shape of every trial
     for (const auto &sh : shapes) {
         for (int bpc : bpcs) {
             ctx->shape = sh;
@@ -799,7 +838,8 @@ pm_status pm_touched_nodes(pm_ctx *ctx, const pm_field *field, const pm_particle
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = 0;
     k.sub_count = in->nsub;
-    k.tile = ctx->shape.wg * ctx->shape.items;
+    const pm::Shape sh = shape_for(ctx, mixed, false, false);
+    k.tile = sh.wg * sh.items;
     const int64_t words = (nbits + 63) / 64;
     PM_HIP(pm::launch_fill(bitmap, words, st), "fill launch");
     PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn, st), "prep launch");

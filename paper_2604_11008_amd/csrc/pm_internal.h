@@ -77,6 +77,9 @@ struct KArgs {
     DWS ws;
     double dt, half_dt, g[3];
     float dtf, half_dtf, gf[3];
+    int32_t drag;        // pm_drag
+    double kappa;        // nonlinear drag: Re_p = kappa sqrt(tau) |V - U|
+    float kappaf;
     int32_t sub_first, sub_count;
     int32_t tile;        // records per tile of this launch shape
     int32_t cpt;         // append: workgroups per destination
@@ -115,7 +118,7 @@ hipError_t launch_popcount(const uint64_t *bitmap, int64_t words,
 hipError_t launch_fill(uint64_t *p, int64_t words, hipStream_t st);
 
 // Workgroups per CU that fit for a launch shape of the fused kernel.
-int step_occupancy(Shape sh, bool mixed, bool halo);
+int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear);
 bool shape_supported(Shape sh);
 
 }  // namespace pm

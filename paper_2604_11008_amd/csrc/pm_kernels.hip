@@ -225,15 +225,31 @@ template <> __device__ __forceinline__ float kdt<float>(const KArgs &a) { return
 template <typename FT> __device__ __forceinline__ FT khdt(const KArgs &a);
 template <> __device__ __forceinline__ double khdt<double>(const KArgs &a) { return a.half_dt; }
 template <> __device__ __forceinline__ float khdt<float>(const KArgs &a) { return a.half_dtf; }
+template <typename FT> __device__ __forceinline__ FT kkappa(const KArgs &a);
+template <> __device__ __forceinline__ double kkappa<double>(const KArgs &a) { return a.kappa; }
+template <> __device__ __forceinline__ float kkappa<float>(const KArgs &a) { return a.kappaf; }
 template <typename FT> __device__ __forceinline__ FT kg(const KArgs &a, int c);
 template <> __device__ __forceinline__ double kg<double>(const KArgs &a, int c) { return a.g[c]; }
 template <> __device__ __forceinline__ float kg<float>(const KArgs &a, int c) { return a.gf[c]; }
 
+// Nonlinear drag factor (Sect. 2.2): Re_p = 2 r |V - U| / nu with r from
+// tau = (2/9)(rho_p/rho) r^2 / nu is Re_p = kappa sqrt(tau) |V - U|, kappa =
+// sqrt(18 / (rho_p/rho nu)) (computed on the host); f = 1 + 0.15 Re_p^0.687.
+// Re_p^0.687 as exp2(0.687 log2 Re_p): Re_p >= 0, and 0 gives 0; the
+// relative error, a few ulp times |0.687 ln Re_p|, stays far inside the
+// tolerance, and it needs much less code and fewer registers than pow.
+template <typename FT>
+__device__ __forceinline__ FT drag_factor(FT kappa, FT tau, const FT s[3])
+{
+    const FT re = kappa * sqrt(tau * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
+    return (FT)1 + (FT)0.15 * exp2((FT)0.687 * log2(re));
+}
+
 // Heun step of one particle.  The stage-2 position X* = X + dt V does not
 // depend on the stage-1 interpolation, so both stencils are located first
 // and fetched in one round trip; most stage-2 stencils fall in the stage-1
-// cell and are not fetched again.
-template <typename FT, bool HALO>
+// cell and are not fetched again.  NL: the nonlinear drag factor, else f = 1.
+template <typename FT, bool HALO, bool NL>
 __device__ __forceinline__ void advance_one(const KArgs &a, double X[3], FT V[3], FT tau,
                                             uint32_t &fl)
 {
@@ -250,12 +266,21 @@ __device__ __forceinline__ void advance_one(const KArgs &a, double X[3], FT V[3]
     stencil_load<FT, HALO>(a.f, c1, S1);
     if (moved)
         stencil_load<FT, HALO>(a.f, c2, S2);
-    FT U1[3], A1[3], Vs[3], U2[3];
+    FT U1[3], A1[3], Vs[3], U2[3], s1[3], s2[3];
     stencil_eval<FT>(S1, fr1, U1);
     const FT it = (FT)1 / tau;
 #pragma unroll
+    for (int c = 0; c < 3; ++c)
+        s1[c] = U1[c] - V[c];
+    if (NL) {
+        const FT f1 = drag_factor<FT>(kkappa<FT>(a), tau, s1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            s1[c] = f1 * s1[c];
+    }
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-        A1[c] = fma(U1[c] - V[c], it, kg<FT>(a, c));
+        A1[c] = fma(s1[c], it, kg<FT>(a, c));
         Vs[c] = fma(dt, A1[c], V[c]);
     }
     if (moved)
@@ -263,8 +288,17 @@ __device__ __forceinline__ void advance_one(const KArgs &a, double X[3], FT V[3]
     else
         stencil_eval<FT>(S1, fr2, U2);
 #pragma unroll
+    for (int c = 0; c < 3; ++c)
+        s2[c] = U2[c] - Vs[c];
+    if (NL) {
+        const FT f2 = drag_factor<FT>(kkappa<FT>(a), tau, s2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            s2[c] = f2 * s2[c];
+    }
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const FT A2 = fma(U2[c] - Vs[c], it, kg<FT>(a, c));
+        const FT A2 = fma(s2[c], it, kg<FT>(a, c));
         X[c] = fma(a.half_dt, (double)V[c] + (double)Vs[c], X[c]);
         V[c] = fma(hdt, A1[c] + A2, V[c]);
     }
@@ -811,8 +845,10 @@ __device__ __forceinline__ void scatter_stash(const KArgs &a, const TileLds<WG, 
 // its next tile.  By then the tiles before it have (almost always) published
 // their aggregates, so the look-back does not wait on slower neighbours.
 // A tile's aggregate never waits on anything, so every walk ends.
-template <int WG, int ITEMS, typename FT, bool HALO>
-__global__ __launch_bounds__(WG) void k_step(const KArgs a)
+// At least two waves per SIMD (one with 8 records per thread, which cannot
+// fit two): the compiler spills a few registers rather than halve occupancy.
+template <int WG, int ITEMS, typename FT, bool HALO, bool NL>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ? 1 : 2))) void k_step(const KArgs a)
 {
     constexpr int NW = WG / 64;
     __shared__ TileLds<WG, ITEMS> L[2];
@@ -859,7 +895,7 @@ __global__ __launch_bounds__(WG) void k_step(const KArgs a)
         for (int k = 0; k < ITEMS; ++k) {
             d[k] = 0xff;
             if (k * WG + tid < nitems) {
-                advance_one<FT, HALO>(a, X[k], V[k], tau[k], fl);
+                advance_one<FT, HALO, NL>(a, X[k], V[k], tau[k], fl);
                 d[k] = classify(a.dc, own, X[k], fl);
             }
         }
@@ -914,7 +950,7 @@ __global__ __launch_bounds__(WG) void k_step(const KArgs a)
 }
 
 // Plain path, steps 1-2: in-place advance of the range's records.
-template <int WG, int ITEMS, typename FT, bool HALO>
+template <int WG, int ITEMS, typename FT, bool HALO, bool NL>
 __global__ __launch_bounds__(WG) void k_advance(const KArgs a)
 {
     __shared__ TileHead H;
@@ -948,7 +984,7 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs a)
         for (int k = 0; k < ITEMS; ++k) {
             const int i = k * WG + tid;
             if (i < nitems) {
-                advance_one<FT, HALO>(a, X[k], V[k], tau[k], fl);
+                advance_one<FT, HALO, NL>(a, X[k], V[k], tau[k], fl);
                 const int64_t p = first + i;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -1401,21 +1437,55 @@ hipError_t launch_prep(const KArgs &a, int mode, hipStream_t st)
     return hipGetLastError();
 }
 
-#define PM_STEP_CASE(W, I)                                                             \
-    if (sh.wg == W && sh.items == I) {                                                 \
-        if (mixed) {                                                                   \
-            if (a.f.halo)                                                              \
-                hipLaunchKernelGGL((k_step<W, I, float, true>), dim3(grid), dim3(W), 0, st, a); \
-            else                                                                       \
-                hipLaunchKernelGGL((k_step<W, I, float, false>), dim3(grid), dim3(W), 0, st, a); \
-        } else {                                                                       \
-            if (a.f.halo)                                                              \
-                hipLaunchKernelGGL((k_step<W, I, double, true>), dim3(grid), dim3(W), 0, st, a); \
-            else                                                                       \
-                hipLaunchKernelGGL((k_step<W, I, double, false>), dim3(grid), dim3(W), 0, st, a); \
-        }                                                                              \
-        return hipGetLastError();                                                      \
+// The fused and advance kernels come in element type x halo x drag law
+// variants; Kern<W, I>::step/advance pick the one for the launch.
+template <int W, int I>
+struct Kern {
+    template <typename FT, bool H, bool NL>
+    static hipError_t step_t(const KArgs &a, int grid, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_step<W, I, FT, H, NL>), dim3(grid), dim3(W), 0, st, a);
+        return hipGetLastError();
     }
+    template <typename FT, bool H, bool NL>
+    static hipError_t advance_t(const KArgs &a, int grid, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_advance<W, I, FT, H, NL>), dim3(grid), dim3(W), 0, st, a);
+        return hipGetLastError();
+    }
+    template <typename FT, bool H, bool NL>
+    static int occupancy_t()
+    {
+        int nb = 1;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, FT, H, NL>), W, 0);
+        return nb;
+    }
+    template <typename FT>
+    static hipError_t step_ft(const KArgs &a, int grid, hipStream_t st)
+    {
+        const bool h = a.f.halo != 0, nl = a.drag != 0;
+        return h ? (nl ? step_t<FT, true, true>(a, grid, st) : step_t<FT, true, false>(a, grid, st))
+                 : (nl ? step_t<FT, false, true>(a, grid, st) : step_t<FT, false, false>(a, grid, st));
+    }
+    template <typename FT>
+    static hipError_t advance_ft(const KArgs &a, int grid, hipStream_t st)
+    {
+        const bool h = a.f.halo != 0, nl = a.drag != 0;
+        return h ? (nl ? advance_t<FT, true, true>(a, grid, st) : advance_t<FT, true, false>(a, grid, st))
+                 : (nl ? advance_t<FT, false, true>(a, grid, st) : advance_t<FT, false, false>(a, grid, st));
+    }
+    template <typename FT>
+    static int occupancy_ft(bool h, bool nl)
+    {
+        return h ? (nl ? occupancy_t<FT, true, true>() : occupancy_t<FT, true, false>())
+                 : (nl ? occupancy_t<FT, false, true>() : occupancy_t<FT, false, false>());
+    }
+};
+
+#define PM_STEP_CASE(W, I)                                                             \
+    if (sh.wg == W && sh.items == I)                                                   \
+        return mixed ? Kern<W, I>::step_ft<float>(a, grid, st)                         \
+                     : Kern<W, I>::step_ft<double>(a, grid, st);
 
 hipError_t launch_step(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st)
 {
@@ -1424,20 +1494,9 @@ hipError_t launch_step(const KArgs &a, Shape sh, bool mixed, int grid, hipStream
 }
 
 #define PM_ADV_CASE(W, I)                                                              \
-    if (sh.wg == W && sh.items == I) {                                                 \
-        if (mixed) {                                                                   \
-            if (a.f.halo)                                                              \
-                hipLaunchKernelGGL((k_advance<W, I, float, true>), dim3(grid), dim3(W), 0, st, a); \
-            else                                                                       \
-                hipLaunchKernelGGL((k_advance<W, I, float, false>), dim3(grid), dim3(W), 0, st, a); \
-        } else {                                                                       \
-            if (a.f.halo)                                                              \
-                hipLaunchKernelGGL((k_advance<W, I, double, true>), dim3(grid), dim3(W), 0, st, a); \
-            else                                                                       \
-                hipLaunchKernelGGL((k_advance<W, I, double, false>), dim3(grid), dim3(W), 0, st, a); \
-        }                                                                              \
-        return hipGetLastError();                                                      \
-    }
+    if (sh.wg == W && sh.items == I)                                                   \
+        return mixed ? Kern<W, I>::advance_ft<float>(a, grid, st)                      \
+                     : Kern<W, I>::advance_ft<double>(a, grid, st);
 
 hipError_t launch_advance(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st)
 {
@@ -1559,18 +1618,11 @@ hipError_t launch_fill(uint64_t *p, int64_t words, hipStream_t st)
 }
 
 #define PM_OCC_CASE(W, I)                                                              \
-    if (sh.wg == W && sh.items == I) {                                                 \
-        if (mixed && halo)                                                             \
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, float, true>), W, 0); \
-        else if (mixed)                                                                \
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, float, false>), W, 0); \
-        else if (halo)                                                                 \
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, double, true>), W, 0); \
-        else                                                                           \
-            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, double, false>), W, 0); \
-    }
+    if (sh.wg == W && sh.items == I)                                                   \
+        nb = mixed ? Kern<W, I>::occupancy_ft<float>(halo, nonlinear)                  \
+                   : Kern<W, I>::occupancy_ft<double>(halo, nonlinear);
 
-int step_occupancy(Shape sh, bool mixed, bool halo)
+int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear)
 {
     int nb = 1;
     PM_SHAPES(PM_OCC_CASE)

@@ -52,7 +52,11 @@ class _Send(C.Structure):
 
 
 class _Params(C.Structure):
-    _fields_ = [("dt", C.c_double), ("g", C.c_double * 3)]
+    _fields_ = [("dt", C.c_double), ("g", C.c_double * 3), ("drag", C.c_int32),
+                ("pad_", C.c_int32), ("nu", C.c_double), ("density_ratio", C.c_double)]
+
+
+DRAG = {"stokes": 0, "nonlinear": 1}
 
 
 class _Tuning(C.Structure):
@@ -246,12 +250,18 @@ class DevicePool:
 
 @dataclass
 class Params:
+    """pm_params: time step, gravity, drag law ("stokes" or "nonlinear") and,
+    for the nonlinear law, nu and rho_p/rho."""
     dt: float
     g: tuple = (0.0, 0.0, 0.0)
+    drag: str = "stokes"
+    nu: float = 1.5e-5
+    density_ratio: float = 843.0
 
     @property
     def c(self):
-        return _Params(float(self.dt), (C.c_double * 3)(*[float(x) for x in self.g]))
+        return _Params(float(self.dt), (C.c_double * 3)(*[float(x) for x in self.g]),
+                       DRAG[self.drag], 0, float(self.nu), float(self.density_ratio))
 
 
 def workspace_bytes(pool_extent, send_extent, nsub):

@@ -24,8 +24,10 @@ class Case:
     """A workload with host (oracle) and device (library) views."""
 
     def __init__(self, name, npart=None, n=None, p=None, order="canonical", mode=None,
-                 face=0.1, edge=0.03, corner=0.02, dt_scale=1.0, slack=0.05, extra=1024):
-        say(f"[case] {name} np={npart} n={n} p={p} order={order} mode={mode}")
+                 face=0.1, edge=0.03, corner=0.02, dt_scale=1.0, slack=0.05, extra=1024,
+                 drag="stokes"):
+        say(f"[case] {name} np={npart} n={n} p={p} order={order} mode={mode} drag={drag}")
+        self.drag = drag
         self.wl = gen.make_workload(name, np_override=npart, n_override=n, p_override=p,
                                     order=order, slack=slack, extra=extra)
         wl = self.wl
@@ -49,7 +51,7 @@ class Case:
         self.field = pm.DeviceField(fdev, wl.n, wl.halo, wl.L, device=self.dev)
         self.dc = pm.Decomp(wl.p, wl.bounds)
         self.sb, self.sc = gen.send_layout(wl.pool.count, face=face, edge=edge, corner=corner)
-        self.params = pm.Params(self.dt, self.g)
+        self.params = pm.Params(self.dt, self.g, drag=drag)
         self.vdt = torch.float32 if self.mode == "mixed" else torch.float64
 
     # device objects
@@ -72,7 +74,8 @@ class Case:
         out = gen.empty_pool(pool.base, pool.cap)
         send = gen.empty_pool(self.sb, self.sc)
         stay, flags = oracle.step(self.ofield, self.odc, self.dt if dt is None else dt,
-                                  self.g, pool, out, send)
+                                  self.g, pool, out, send, drag=self.drag,
+                                  nu=self.params.nu, density_ratio=self.params.density_ratio)
         return out, send, stay, flags
 
 

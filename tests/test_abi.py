@@ -3,6 +3,7 @@ include/pm.h declares; the binding's structures match the header's layout."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -30,14 +31,45 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-def test_binding_struct_layout_matches_header():
+def header_layout(tmp_path):
+    """sizeof and field offsets of the header's structs, from a C compiler."""
+    probes = {
+        "pm_field": ["n", "halo", "L", "dtype", "u"],
+        "pm_decomp": ["p", "bounds"],
+        "pm_particles": ["nsub", "vdtype", "base", "cap", "count", "x", "v", "tau", "id"],
+        "pm_sendbufs": ["base", "cap", "count", "x", "v", "tau", "id"],
+        "pm_params": ["dt", "g", "drag", "nu", "density_ratio"],
+        "pm_tuning": ["wg", "items", "blocks_per_cu"],
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pm.h"', 'int main(void) {']
+    for st, fields in probes.items():
+        lines.append(f'printf("{st} sizeof %zu\\n", sizeof({st}));')
+        for f in fields:
+            lines.append(f'printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), "-o", str(exe), str(src)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    res = {}
+    for line in out.splitlines():
+        st, f, v = line.split()
+        res[(st, f)] = int(v)
+    return probes, res
+
+
+def test_binding_struct_layout_matches_header(tmp_path):
     from paper_2604_11008_amd import pm
-    assert ctypes.sizeof(pm._Field) == 72
-    assert ctypes.sizeof(pm._Decomp) == 40
-    assert ctypes.sizeof(pm._Particles) == 96
-    assert ctypes.sizeof(pm._Send) == 88
-    assert ctypes.sizeof(pm._Params) == 32
-    assert ctypes.sizeof(pm._Tuning) == 16
+    probes, ref = header_layout(tmp_path)
+    cls = {"pm_field": pm._Field, "pm_decomp": pm._Decomp, "pm_particles": pm._Particles,
+           "pm_sendbufs": pm._Send, "pm_params": pm._Params, "pm_tuning": pm._Tuning}
+    for st, fields in probes.items():
+        c = cls[st]
+        assert ctypes.sizeof(c) == ref[(st, "sizeof")], st
+        for f in fields:
+            assert getattr(c, f).offset == ref[(st, f)], (st, f)
 
 
 def test_host_only_calls():

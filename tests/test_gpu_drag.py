@@ -1,0 +1,113 @@
+"""GPU parity of the nonlinear drag law (Sect. 2.2: f = 1 + 0.15 Re_p^0.687,
+Re_p = 2 r |V - U| / nu, r from tau = (2/9)(rho_p/rho) r^2 / nu; nu = 1.5e-5,
+rho_p/rho = 843 in the units of the synthetic fields) against the oracle:
+the in-place advance within 1e-12, the fused step with bit-exact migration,
+and fused == plain bitwise.  Each case also checks that the law changes the
+result, so a silently ignored drag flag fails."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_cases import Case, assert_same_device_pools, compare_pools, say, seg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("name,npart,n,p", [("C1", 20000, 32, (2, 2, 2)),
+                                            ("C2", 30000, 32, (1, 1, 1))])
+def test_nonlinear_advance_matches_oracle(name, npart, n, p):
+    say(f"[test] nonlinear interp_advance {name}")
+    c = Case(name, npart, n, p, drag="nonlinear")
+    pin = c.pin()
+    ctx = c.ctx(pin, c.send())
+    ctx.interp_advance(c.field, pin, c.params)
+    assert ctx.get_status() == 0
+    got = pin.to_host()
+    changed = 0.0
+    for q in range(c.dc.nsub):
+        s = seg(c.host, q)
+        args = (c.ofield, c.host.x[:, s], c.host.v[:, s], c.host.tau[s], c.dt, c.g)
+        xr, vr, _ = oracle.advance(*args, drag="nonlinear")
+        _, vs, _ = oracle.advance(*args)
+        ex = np.abs(got.x[:, s] - xr) / np.maximum(np.abs(xr), c.wl.L / c.wl.n)
+        ev = np.abs(got.v[:, s] - vr) / max(1.0, np.abs(vr).max())
+        assert ex.max() <= 1e-12 and ev.max() <= 1e-12, (ex.max(), ev.max())
+        changed = max(changed, float(np.abs(vr - vs).max()))
+    say(f"  max |V_nonlinear - V_stokes| {changed:.2e}")
+    assert changed > 1e-6
+
+
+@pytest.mark.parametrize("name,npart,n,p", [("C1", None, None, None),
+                                            ("C2", 40000, 32, None),
+                                            ("C3", 50000, 32, (4, 4, 4))])
+def test_nonlinear_step_matches_oracle(name, npart, n, p):
+    say(f"[test] nonlinear step {name}")
+    c = Case(name, npart, n, p, drag="nonlinear")
+    pin, send = c.pin(), c.send()
+    pout = c.pout(pin.size)
+    ctx = c.ctx(pin, send)
+    ctx.step(c.field, c.dc, pin, pout, send, c.params)
+    flags = ctx.get_status()
+    ref_out, ref_send, _, oflags = c.oracle_step()
+    assert flags == oflags == 0
+    delta = c.wl.L / c.wl.n
+    compare_pools(send.to_host(), ref_send, c.dc.nsub * 27, c.wl.L, delta, what="send")
+    ex, ev = compare_pools(pout.to_host(), ref_out, c.dc.nsub, c.wl.L, delta, what="out")
+    say(f"  migrants {int(ref_send.count.sum())}; max err x {ex:.2e} v {ev:.2e}")
+
+
+def test_nonlinear_fused_equals_plain_bitwise():
+    say("[test] nonlinear fused == plain")
+    c = Case("C2S", 80000, 32, (8, 8, 8), drag="nonlinear")
+    c.params.dt = min(c.dt, 0.015)
+    pin = c.pin()
+    send_a, send_b = c.send(), c.send()
+    out_a, out_b = c.pout(pin.size), c.pout(pin.size)
+    ctx = c.ctx(pin, send_a)
+    ctx.step(c.field, c.dc, pin, out_a, send_a, c.params)
+    plain_in = c.pin()
+    ctx.interp_advance(c.field, plain_in, c.params)
+    ctx.classify_scan_pack(c.dc, plain_in, send_b)
+    ctx.compact_append(c.dc, plain_in, send_b, out_b)
+    assert ctx.get_status() == 0
+    assert_same_device_pools(out_a, out_b, c.dc.nsub, "out")
+    assert_same_device_pools(send_a, send_b, c.dc.nsub * 27, "send")
+
+
+def test_bad_drag_parameters_are_argument_errors():
+    from paper_2604_11008_amd import pm
+    c = Case("C1", 2000, 16, (1, 1, 1))
+    pin = c.pin()
+    ctx = c.ctx(pin, c.send())
+    for kw in (dict(drag="nonlinear", nu=0.0), dict(drag="nonlinear", density_ratio=-1.0),
+               dict(drag="nonlinear", nu=float("nan"))):
+        with pytest.raises(pm.PMError, match="nonlinear drag"):
+            ctx.interp_advance(c.field, pin, pm.Params(c.dt, c.g, **kw))
+
+
+def test_default_launch_shape_follows_the_variant():
+    from paper_2604_11008_amd import pm
+    say("[test] per-variant default shapes")
+    c = Case("C3", 50000, 32, (4, 4, 4), drag="nonlinear")
+    pin, send = c.pin(), c.send()
+    pout = c.pout(pin.size)
+    ctx = c.ctx(pin, send)
+    stokes = pm.Params(c.dt, c.g)
+    ctx.step(c.field, c.dc, pin, pout, send, c.params)
+    assert ctx.get_tuning()[:2] == (256, 2)
+    ctx.step(c.field, c.dc, pin, pout, send, stokes)
+    assert ctx.get_tuning()[:2] == (256, 4)
+    ctx.set_tuning(256, 1)
+    ctx.step(c.field, c.dc, pin, pout, send, c.params)
+    assert ctx.get_tuning()[:2] == (256, 1)
+    ctx.set_tuning(0, 0)
+    ctx.step(c.field, c.dc, pin, pout, send, c.params)
+    assert ctx.get_tuning()[:2] == (256, 2)
+    assert ctx.get_status() == 0
