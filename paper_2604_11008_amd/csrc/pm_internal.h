@@ -119,6 +119,13 @@ hipError_t launch_fill(uint64_t *p, int64_t words, hipStream_t st);
 
 // Workgroups per CU that fit for a launch shape of the fused kernel.
 int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear);
+// per element type (pm_step_f64.hip, pm_step_f32.hip)
+hipError_t launch_step_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
+hipError_t launch_step_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
+hipError_t launch_advance_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
+hipError_t launch_advance_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
+int step_occupancy_f64(Shape sh, bool halo, bool nonlinear);
+int step_occupancy_f32(Shape sh, bool halo, bool nonlinear);
 bool shape_supported(Shape sh);
 
 }  // namespace pm
