@@ -64,8 +64,8 @@ def lib():
 # --- C structures (mirroring oracle.h) ---------------------------------------
 
 class _Field(C.Structure):
-    _fields_ = [("n", C.c_int * 3), ("halo", C.c_int), ("L", C.c_double * 3),
-                ("u", C.c_void_p * 3)]
+    _fields_ = [("n", C.c_int * 3), ("halo", C.c_int), ("stagger", C.c_int),
+                ("L", C.c_double * 3), ("u", C.c_void_p * 3)]
 
 
 class _Decomp(C.Structure):
@@ -101,17 +101,20 @@ def _f64(a):
 
 
 class Field:
-    """Velocity field as stored: three flat float64 arrays, (n or n+2)^3."""
+    """Velocity field as stored: three flat float64 arrays, (n or n+2)^3;
+    stagger=True: MAC arrangement (component c on the faces normal to axis c)."""
 
-    def __init__(self, u, n, halo, L=2.0 * np.pi):
+    def __init__(self, u, n, halo, L=2.0 * np.pi, stagger=False):
         self.u = [_f64(np.asarray(c).reshape(-1)) for c in u]
         self.n = (n, n, n) if np.isscalar(n) else tuple(n)
         self.halo = int(halo)
+        self.stagger = int(bool(stagger))
         self.L = (L, L, L) if np.isscalar(L) else tuple(L)
         st = [k + 2 * self.halo for k in self.n]
         if any(c.size != st[0] * st[1] * st[2] for c in self.u):
             raise ValueError("field size does not match n and halo")
-        self._c = _Field((C.c_int * 3)(*self.n), self.halo, (C.c_double * 3)(*self.L),
+        self._c = _Field((C.c_int * 3)(*self.n), self.halo, self.stagger,
+                         (C.c_double * 3)(*self.L),
                          (C.c_void_p * 3)(*[c.ctypes.data for c in self.u]))
 
     @property

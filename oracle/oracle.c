@@ -38,13 +38,13 @@
 /* ------------------------------------------------------------------ */
 
 /* Stored index of the two corners along one axis, and the fraction. */
-static unsigned axis_corners(const orc_field *f, int a, double X,
+static unsigned axis_corners(const orc_field *f, int a, double X, double half,
                              int64_t c[2], double *frac)
 {
     unsigned flags = 0;
     const int n = f->n[a];
     const double r = (double)n / f->L[a];
-    const double s = X * r - 0.5;
+    const double s = X * r - half;
     const double fl = floor(s);
     int64_t i;
 
@@ -97,8 +97,31 @@ unsigned orc_interp(const orc_field *f, const double X[3], double U[3])
     const int64_t sx = f->n[0] + 2 * f->halo;
     const int64_t sy = f->n[1] + 2 * f->halo;
 
+    if (f->stagger) {
+        /* MAC: component comp sits on the faces normal to axis comp, so its
+         * nodes are offset by half a cell along that axis only */
+        for (int comp = 0; comp < 3; ++comp) {
+            for (int a = 0; a < 3; ++a)
+                flags |= axis_corners(f, a, X[a], a == comp ? 0.0 : 0.5, c[a], &fr[a]);
+            U[comp] = 0.0;
+            for (int cz = 0; cz < 2; ++cz) {
+                for (int cy = 0; cy < 2; ++cy) {
+                    for (int cx = 0; cx < 2; ++cx) {
+                        const double wx = cx ? fr[0] : 1.0 - fr[0];
+                        const double wy = cy ? fr[1] : 1.0 - fr[1];
+                        const double wz = cz ? fr[2] : 1.0 - fr[2];
+                        const double w = (wx * wy) * wz;
+                        const int64_t node = c[0][cx] + sx * (c[1][cy] + sy * c[2][cz]);
+                        U[comp] = U[comp] + w * f->u[comp][node];
+                    }
+                }
+            }
+        }
+        return flags;
+    }
+
     for (int a = 0; a < 3; ++a)
-        flags |= axis_corners(f, a, X[a], c[a], &fr[a]);
+        flags |= axis_corners(f, a, X[a], 0.5, c[a], &fr[a]);
 
     for (int comp = 0; comp < 3; ++comp)
         U[comp] = 0.0;

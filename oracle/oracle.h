@@ -45,7 +45,11 @@ extern "C" {
 #define ORC_STAY 13           /* direction code of "no boundary crossed"       */
 
 /* Velocity field on a uniform grid of a box [0,L0)x[0,L1)x[0,L2).
- * Node (i,j,k) sits at the cell centre ((i+1/2)L0/n0, ...).
+ * stagger == 0 (collocated): node (i,j,k) of every component sits at the
+ * cell centre ((i+1/2)L0/n0, ...).  stagger == 1 (MAC): component c's node
+ * (i,j,k) sits on the face of cell (i,j,k) normal to axis c, at offset 0
+ * along axis c and 1/2 along the others (u_x at (i L0/n0, (j+1/2)L1/n1,
+ * (k+1/2)L2/n2), ...).
  * halo == 0: arrays hold n0*n1*n2 values, indices taken modulo n (periodic).
  * halo == 1: arrays hold (n0+2)(n1+2)(n2+2) values; stored index i+1 is node
  *            i, and stored 0 and n+1 are the halo nodes -1 and n.
@@ -53,6 +57,7 @@ extern "C" {
 typedef struct {
     int n[3];
     int halo;
+    int stagger;
     double L[3];
     const double *u[3];
 } orc_field;
