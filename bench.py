@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--drag", default="stokes", choices=["stokes", "nonlinear"],
                     help="drag law: Stokes (f = 1) or the paper's nonlinear correction "
                          "(nu = 1.5e-5, rho_p/rho = 843 in the field's units)")
+    ap.add_argument("--stagger", action="store_true",
+                    help="read the field as MAC-staggered (component c on the faces "
+                         "normal to axis c)")
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
     ap.add_argument("--tune", default=None, help="wg,items[,blocks_per_cu] or 'auto'")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
@@ -73,11 +76,11 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(wl, seconds, drag="stokes"):
+def cpu_baseline(wl, seconds, drag="stokes", stagger=False):
     """The oracle, single-threaded, on whole steps of the same workload."""
     import oracle
     pool = wl.pool
-    of = oracle.Field(wl.stored_field(np.float64), wl.n, wl.halo, wl.L)
+    of = oracle.Field(wl.stored_field(np.float64), wl.n, wl.halo, wl.L, stagger=stagger)
     od = oracle.Decomp(wl.p, wl.bounds)
     sb, sc = gen.send_layout(pool.count, face=0.05, edge=0.01, corner=0.005)
     npart = int(pool.count.sum())
@@ -164,7 +167,8 @@ def main():
         wl.pool.tau = wl.pool.tau.astype(cast)
         wl.mode = "mixed" if mixed else "f64"
     fdt = np.float32 if mixed else np.float64
-    field = pm.DeviceField(wl.stored_field(fdt), wl.n, wl.halo, wl.L, device=dev)
+    field = pm.DeviceField(wl.stored_field(fdt), wl.n, wl.halo, wl.L, device=dev,
+                           stagger=args.stagger)
     dc = pm.Decomp(wl.p, wl.bounds)
     vdt = torch.float32 if mixed else torch.float64
     pool = wl.pool
@@ -334,7 +338,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(wl, args.cpu_seconds, args.drag)
+        cpu = cpu_baseline(wl, args.cpu_seconds, args.drag, args.stagger)
         # the paper's CPU-delegated estimate (Sect. 3.2.2) for this host and workload:
         # arrays out and back over the link, packed and unpacked at one core's bandwidth
         h2d, d2h = link_gbps(torch, dev)
@@ -355,7 +359,8 @@ def main():
         "dtype": "mixed-f32/f64" if mixed else "f64", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}" +
                    (f" (run at {args.precision})" if args.precision != "auto" else "") +
-                   (", nonlinear drag" if args.drag == "nonlinear" else ""),
+                   (", nonlinear drag" if args.drag == "nonlinear" else "") +
+                   (", MAC-staggered field" if args.stagger else ""),
                    "particles": npart, "grid": wl.n, "halo": wl.halo,
                    "subdomains": list(wl.p), "graph": bool(args.graph),
                    "tuning": list(ctx.get_tuning())},

@@ -91,13 +91,18 @@ typedef enum { PM_F64 = 0, PM_F32 = 1 } pm_dtype;
  *   halo == 0: n0*n1*n2 values, node indices taken modulo n (periodic);
  *   halo == 1: (n0+2)(n1+2)(n2+2) values, stored index i+1 holds node i, so
  *              stored 0 and n+1 are the halo nodes -1 and n (for a periodic
- *              box: copies of nodes n-1 and 0). */
+ *              box: copies of nodes n-1 and 0).
+ * stagger == 0: collocated, node (i,j,k) of every component at the cell
+ * centre ((i+1/2)L0/n0, ...), as the paper interpolates (Sect. 2.2);
+ * stagger == 1: MAC arrangement, as its fluid solver stores the velocity
+ * (Sect. 2.1): component c's node (i,j,k) on the face of cell (i,j,k)
+ * normal to axis c, offset 0 along axis c and 1/2 along the others. */
 typedef struct {
     int32_t n[3];
     int32_t halo;
     double L[3];
     int32_t dtype;      /* pm_dtype */
-    int32_t pad_;
+    int32_t stagger;    /* 0 collocated, 1 MAC */
     const void *u[3];
 } pm_field;
 
@@ -167,7 +172,8 @@ typedef struct {
 /* Launch shape of the tile kernels: workgroup size (256 or 512), records
  * per thread (1, 2, 4 or 8); tile = wg*items records.  wg = 0 in
  * pm_set_tuning selects the per-variant defaults (256 x 4; 256 x 2 for FP64
- * periodic fields with the nonlinear drag law), which a context uses until
+ * periodic fields with the nonlinear drag law or the MAC arrangement), which
+ * a context uses until
  * pm_set_tuning or pm_autotune fixes a shape; pm_get_tuning then reports the
  * shape of the last launch.  blocks_per_cu is the persistent grid's
  * workgroups per compute unit: 0 = the runtime's occupancy estimate; an
@@ -273,7 +279,10 @@ pm_status pm_kernel_times(pm_ctx *ctx, int32_t *n, double *total_ms, float *ms,
 /* Untimed diagnostic: number of distinct field nodes read by the stage-1
  * and stage-2 stencils of one pm_step from `in` (an exact count, through a
  * bitmap of nbits >= number of stored nodes bits, caller-owned device
- * memory of (nbits+63)/64 uint64, cleared here).  Synchronous. */
+ * memory of (nbits+63)/64 uint64, cleared here).  For a MAC field, whose
+ * components have their own stencils, the bitmap needs 3 x the stored nodes
+ * and the result is the number of distinct (component, node) values read,
+ * divided by 3.  Synchronous. */
 pm_status pm_touched_nodes(pm_ctx *ctx, const pm_field *field,
                            const pm_particles *in, const pm_params *params,
                            uint64_t *bitmap, int64_t nbits, void *stream,

@@ -12,7 +12,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpm.so")
-SOURCES = ["pm_step_f64.hip", "pm_step_f32.hip", "pm_kernels.hip", "pm_api.hip"]
+SOURCES = ["pm_step_f64.hip", "pm_step_f32.hip", "pm_mac_f64.hip", "pm_mac_f32.hip",
+           "pm_kernels.hip", "pm_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -118,6 +118,8 @@ pm_status conv_field(const pm_field *f, pm::DField &d, bool &mixed)
         return arg_error("field.halo must be 0 or 1");
     if (f->dtype != PM_F64 && f->dtype != PM_F32)
         return arg_error("field.dtype must be PM_F64 or PM_F32");
+    if (f->stagger != 0 && f->stagger != 1)
+        return arg_error("field.stagger must be 0 or 1");
     for (int a = 0; a < 3; ++a) {
         if (f->n[a] < 2 || f->n[a] > (1 << 20))
             return arg_error("field.n[%d] = %d out of range", a, f->n[a]);
@@ -136,6 +138,7 @@ pm_status conv_field(const pm_field *f, pm::DField &d, bool &mixed)
         d.r[a] = (double)f->n[a] / f->L[a];
     }
     d.halo = f->halo;
+    d.stagger = f->stagger;
     d.sx = sx;
     d.sxy = sx * sy;
     mixed = f->dtype == PM_F32;
@@ -259,24 +262,28 @@ pm_status check_range(pm_ctx *ctx, int32_t nsub, int32_t first, int32_t count)
 
 // Launch shape of a call: the tuned one, else a measured default — 256
 // threads x 4 records, except the FP64 periodic kernels with the nonlinear
-// drag law, whose 4-record variant runs out of registers (x 2 records).
-pm::Shape shape_for(pm_ctx *ctx, bool mixed, bool halo, bool nonlinear)
+// drag law or a MAC field, whose 4-record variants run out of registers
+// (x 2 records).
+pm::Shape shape_for(pm_ctx *ctx, bool mixed, bool halo, bool nonlinear, bool stagger)
 {
     pm::Shape sh = ctx->shape;
     if (ctx->shape_auto)
-        sh = (!mixed && !halo && nonlinear) ? pm::Shape{256, 2} : pm::Shape{256, 4};
+        sh = (!mixed && !halo && (nonlinear || stagger)) ? pm::Shape{256, 2}
+                                                         : pm::Shape{256, 4};
     ctx->last_shape = sh;
     return sh;
 }
 
-int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed, bool halo, bool nonlinear)
+int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed, bool halo, bool nonlinear,
+                    bool stagger)
 {
     // An explicit figure may exceed the runtime's occupancy estimate: workgroups
     // that do not fit start as others retire, and since tiles are claimed by
     // ticket when a workgroup runs, no running workgroup waits on one that has
     // not started.
     const int per = ctx->blocks_per_cu > 0 ? ctx->blocks_per_cu
-                                           : pm::step_occupancy(sh, mixed, halo, nonlinear);
+                                           : pm::step_occupancy(sh, mixed, halo, nonlinear,
+                                                                stagger);
     return std::max(1, ctx->cus * per);
 }
 
@@ -285,7 +292,7 @@ int append_cpt(int32_t count) { return std::max(1, 2048 / std::max(1, count)); }
 // Queue the fused step (prep, fused kernel, exchange) on `st`.
 pm_status queue_step(pm_ctx *ctx, pm::KArgs &k, bool mixed, hipStream_t st, bool timed)
 {
-    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0);
+    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
     k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(k.sub_count);
     PM_HIP(pm::launch_prep(k,
@@ -296,7 +303,7 @@ pm_status queue_step(pm_ctx *ctx, pm::KArgs &k, bool mixed, hipStream_t st, bool
            "prep launch");
     if (timed)
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount], st), "event record");
-    PM_HIP(pm::launch_step(k, sh, mixed, persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0), st),
+    PM_HIP(pm::launch_step(k, sh, mixed, persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0), st),
            "fused step launch");
     if (timed) {
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount + 1], st), "event record");
@@ -447,10 +454,10 @@ pm_status pm_interp_advance(pm_ctx *ctx, const pm_field *field, pm_particles *in
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = sub_first;
     k.sub_count = sub_count;
-    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0);
+    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
     k.tile = sh.wg * sh.items;
     PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn, st), "prep launch");
-    PM_HIP(pm::launch_advance(k, sh, mixed, persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0), st),
+    PM_HIP(pm::launch_advance(k, sh, mixed, persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0), st),
            "advance launch");
     return PM_OK;
 }
@@ -484,14 +491,14 @@ pm_status pm_classify_scan_pack(pm_ctx *ctx, const pm_decomp *decomp, const pm_p
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = sub_first;
     k.sub_count = sub_count;
-    const pm::Shape sh = shape_for(ctx, mixed, false, false);
+    const pm::Shape sh = shape_for(ctx, mixed, false, false, false);
     k.tile = sh.wg * sh.items;
     PM_HIP(pm::launch_prep(k,
                            pm::kPrepTiles | pm::kPrepStaging | pm::kPrepZeroLb |
                                pm::kPrepZeroCounts | pm::kPrepCheckIn | pm::kPrepCheckSend,
                            st),
            "prep launch");
-    PM_HIP(pm::launch_classify(k, sh, mixed, persistent_grid(ctx, sh, mixed, false, false), st),
+    PM_HIP(pm::launch_classify(k, sh, mixed, persistent_grid(ctx, sh, mixed, false, false, false), st),
            "classify launch");
     PM_HIP(pm::launch_route(k, mixed, false, st), "route launch");
     return PM_OK;
@@ -527,14 +534,14 @@ pm_status pm_compact_append(pm_ctx *ctx, const pm_decomp *decomp, const pm_parti
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = sub_first;
     k.sub_count = sub_count;
-    const pm::Shape sh = shape_for(ctx, mixed, false, false);
+    const pm::Shape sh = shape_for(ctx, mixed, false, false, false);
     k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(sub_count);
     PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn | pm::kPrepCheckOut |
                                   pm::kPrepCheckSend,
                            st),
            "prep launch");
-    PM_HIP(pm::launch_compact(k, sh, mixed, persistent_grid(ctx, sh, mixed, false, false), st),
+    PM_HIP(pm::launch_compact(k, sh, mixed, persistent_grid(ctx, sh, mixed, false, false, false), st),
            "compact launch");
     const int grid = std::min(4096, sub_count * k.cpt);
     PM_HIP(pm::launch_append(k, mixed, std::max(1, grid), st), "append launch");
@@ -587,7 +594,7 @@ pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
         return queue_step(ctx, k, mixed, st, timed);
     }
     // graph path: one captured graph per distinct argument set and shape
-    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0);
+    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
     k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(k.sub_count);
     std::vector<unsigned char> key(sizeof k + sizeof sh + sizeof(int));
@@ -766,7 +773,7 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
     PM_HIP(hipEventCreate(&e0), "event create");
     PM_HIP(hipEventCreate(&e1), "event create");
     float best = 1e30f;
-    pm::Shape best_sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0);
+    pm::Shape best_sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
     int best_bpc = ctx->blocks_per_cu;
     ctx->shape_auto = false;  // the sweep sets the shape of every trial
     for (const auto &sh : shapes) {
@@ -832,13 +839,13 @@ pm_status pm_touched_nodes(pm_ctx *ctx, const pm_field *field, const pm_particle
         s = check_range(ctx, in->nsub, 0, in->nsub);
     if (s)
         return s;
-    const int64_t nodes = k.f.sxy * (field->n[2] + 2 * field->halo);
+    const int64_t nodes = k.f.sxy * (field->n[2] + 2 * field->halo) * (k.f.stagger ? 3 : 1);
     if (!bitmap || nbits < nodes)
         return arg_error("bitmap needs %lld bits", (long long)nodes);
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = 0;
     k.sub_count = in->nsub;
-    const pm::Shape sh = shape_for(ctx, mixed, false, false);
+    const pm::Shape sh = shape_for(ctx, mixed, false, false, false);
     k.tile = sh.wg * sh.items;
     const int64_t words = (nbits + 63) / 64;
     PM_HIP(pm::launch_fill(bitmap, words, st), "fill launch");
@@ -850,7 +857,7 @@ pm_status pm_touched_nodes(pm_ctx *ctx, const pm_field *field, const pm_particle
     unsigned long long h = 0;
     PM_HIP(hipMemcpyAsync(&h, cnt, sizeof h, hipMemcpyDeviceToHost, st), "count read");
     PM_HIP(hipStreamSynchronize(st), "stream sync");
-    *touched = (int64_t)h;
+    *touched = k.f.stagger ? (int64_t)((h + 1) / 3) : (int64_t)h;
     return PM_OK;
 }
 

@@ -88,13 +88,15 @@ __device__ __forceinline__ void owner_xyz(const DDecomp &dc, int s, int own[3])
 // trilinear interpolation (Sect. 2.2)
 // ---------------------------------------------------------------------------
 
-// Stored corner indices of one axis and the cell fraction (float64).
+// Stored corner indices of one axis and the cell fraction (float64); half is
+// the nodes' offset in cells: 1/2 for cell centres, 0 for the faces of a
+// MAC component along its own axis.
 template <bool HALO>
-__device__ __forceinline__ double axis_corner(const DField &f, int a, double X, int &c0,
-                                              uint32_t &fl)
+__device__ __forceinline__ double axis_corner(const DField &f, int a, double X, double half,
+                                              int &c0, uint32_t &fl)
 {
     const int n = f.n[a];
-    const double s = X * f.r[a] - 0.5;
+    const double s = X * f.r[a] - half;
     const double fs = floor(s);
     int i;
     if (s != s) {
@@ -144,7 +146,7 @@ __device__ __forceinline__ void stencil_index(const DField &f, const double X[3]
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-        fr[a] = (FT)axis_corner<HALO>(f, a, X[a], c0[a], fl);
+        fr[a] = (FT)axis_corner<HALO>(f, a, X[a], 0.5, c0[a], fl);
 }
 
 // Two x-adjacent node values in one vector load (16 bytes for double, 8 for
@@ -208,11 +210,81 @@ __device__ __forceinline__ void stencil_eval(const FT v[3][8], const FT fr[3], F
     }
 }
 
-// U(X) by trilinear interpolation (Sect. 2.2).
+// MAC fields: each component has its own stencil.  Along axis a,
+// component c uses the face-centred corner (offset 0) if a == c, else the
+// cell-centred one (offset 1/2); both are found once per axis.
 template <typename FT, bool HALO>
+__device__ __forceinline__ void mac_index(const DField &f, const double X[3], int c0[3][3],
+                                          FT fr[3][3], uint32_t &fl)
+{
+    int cc[3], cf[3];
+    FT fc[3], ff[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        fc[a] = (FT)axis_corner<HALO>(f, a, X[a], 0.5, cc[a], fl);
+        ff[a] = (FT)axis_corner<HALO>(f, a, X[a], 0.0, cf[a], fl);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            c0[c][a] = a == c ? cf[a] : cc[a];
+            fr[c][a] = a == c ? ff[a] : fc[a];
+        }
+}
+
+// The 8 node values of one component's stencil, v[2*r + x] as in
+// stencil_load (x pairs in one load, the periodic wrap handled the same way).
+template <typename FT, bool HALO>
+__device__ __forceinline__ void comp_load(const DField &f, int comp, const int c0[3], FT v[8])
+{
+    const int cx1 = next_corner<HALO>(f, 0, c0[0]);
+    const int cy1 = next_corner<HALO>(f, 1, c0[1]);
+    const int cz1 = next_corner<HALO>(f, 2, c0[2]);
+    const int64_t r[4] = {f.sx * (int64_t)c0[1] + f.sxy * (int64_t)c0[2],
+                          f.sx * (int64_t)cy1 + f.sxy * (int64_t)c0[2],
+                          f.sx * (int64_t)c0[1] + f.sxy * (int64_t)cz1,
+                          f.sx * (int64_t)cy1 + f.sxy * (int64_t)cz1};
+    const FT *u = (const FT *)f.u[comp];
+    const bool wrap = !HALO && cx1 != c0[0] + 1;
+    const int xa = wrap ? c0[0] - 1 : c0[0];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        load_pair<FT>(u + r[k] + xa, v[2 * k], v[2 * k + 1]);
+    if (wrap) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[2 * k] = v[2 * k + 1];
+            v[2 * k + 1] = u[r[k] + cx1];
+        }
+    }
+}
+
+template <typename FT>
+__device__ __forceinline__ FT comp_eval(const FT v[8], const FT fr[3])
+{
+    const FT l00 = lerp(v[0], v[1], fr[0]), l10 = lerp(v[2], v[3], fr[0]);
+    const FT l01 = lerp(v[4], v[5], fr[0]), l11 = lerp(v[6], v[7], fr[0]);
+    return lerp(lerp(l00, l10, fr[1]), lerp(l01, l11, fr[1]), fr[2]);
+}
+
+// U(X) by trilinear interpolation (Sect. 2.2); STAG: from a MAC field.
+template <typename FT, bool HALO, bool STAG = false>
 __device__ __forceinline__ void interp(const DField &f, const double X[3], FT U[3],
                                        uint32_t &fl)
 {
+    if (STAG) {
+        int c0[3][3];
+        FT fr[3][3], v[3][8];
+        mac_index<FT, HALO>(f, X, c0, fr, fl);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            comp_load<FT, HALO>(f, c, c0[c], v[c]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            U[c] = comp_eval<FT>(v[c], fr[c]);
+        return;
+    }
     int c0[3];
     FT fr[3], v[3][8];
     stencil_index<FT, HALO>(f, X, c0, fr, fl);
@@ -255,25 +327,52 @@ __device__ __forceinline__ FT drag_factor(FT kappa, FT tau, const FT s[3])
 // depend on the stage-1 interpolation, so both stencils are located first
 // and fetched in one round trip; most stage-2 stencils fall in the stage-1
 // cell and are not fetched again.  NL: the nonlinear drag factor, else f = 1.
-template <typename FT, bool HALO, bool NL>
+template <typename FT, bool HALO, bool NL, bool STAG>
 __device__ __forceinline__ void advance_one(const KArgs &a, double X[3], FT V[3], FT tau,
                                             uint32_t &fl)
 {
     const FT dt = kdt<FT>(a), hdt = khdt<FT>(a);
-    int c1[3], c2[3];
-    FT fr1[3], fr2[3], S1[3][8], S2[3][8];
     double Xs[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
         Xs[c] = fma(a.dt, (double)V[c], X[c]);
-    stencil_index<FT, HALO>(a.f, X, c1, fr1, fl);
-    stencil_index<FT, HALO>(a.f, Xs, c2, fr2, fl);
-    const bool moved = c2[0] != c1[0] || c2[1] != c1[1] || c2[2] != c1[2];
-    stencil_load<FT, HALO>(a.f, c1, S1);
-    if (moved)
-        stencil_load<FT, HALO>(a.f, c2, S2);
-    FT U1[3], A1[3], Vs[3], U2[3], s1[3], s2[3];
-    stencil_eval<FT>(S1, fr1, U1);
+    FT U1[3], U2[3];
+    if (STAG) {
+        int c1[3][3], c2[3][3];
+        FT fr1[3][3], fr2[3][3], S1[3][8], S2[3][8];
+        mac_index<FT, HALO>(a.f, X, c1, fr1, fl);
+        mac_index<FT, HALO>(a.f, Xs, c2, fr2, fl);
+        bool moved[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            moved[c] = c2[c][0] != c1[c][0] || c2[c][1] != c1[c][1] || c2[c][2] != c1[c][2];
+            comp_load<FT, HALO>(a.f, c, c1[c], S1[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (moved[c])
+                comp_load<FT, HALO>(a.f, c, c2[c], S2[c]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            U1[c] = comp_eval<FT>(S1[c], fr1[c]);
+            U2[c] = moved[c] ? comp_eval<FT>(S2[c], fr2[c]) : comp_eval<FT>(S1[c], fr2[c]);
+        }
+    } else {
+        int c1[3], c2[3];
+        FT fr1[3], fr2[3], S1[3][8], S2[3][8];
+        stencil_index<FT, HALO>(a.f, X, c1, fr1, fl);
+        stencil_index<FT, HALO>(a.f, Xs, c2, fr2, fl);
+        const bool moved = c2[0] != c1[0] || c2[1] != c1[1] || c2[2] != c1[2];
+        stencil_load<FT, HALO>(a.f, c1, S1);
+        if (moved)
+            stencil_load<FT, HALO>(a.f, c2, S2);
+        stencil_eval<FT>(S1, fr1, U1);
+        if (moved)
+            stencil_eval<FT>(S2, fr2, U2);
+        else
+            stencil_eval<FT>(S1, fr2, U2);
+    }
+    FT A1[3], Vs[3], s1[3], s2[3];
     const FT it = (FT)1 / tau;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -289,10 +388,6 @@ __device__ __forceinline__ void advance_one(const KArgs &a, double X[3], FT V[3]
         A1[c] = fma(s1[c], it, kg<FT>(a, c));
         Vs[c] = fma(dt, A1[c], V[c]);
     }
-    if (moved)
-        stencil_eval<FT>(S2, fr2, U2);
-    else
-        stencil_eval<FT>(S1, fr2, U2);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
         s2[c] = U2[c] - Vs[c];
@@ -853,7 +948,7 @@ __device__ __forceinline__ void scatter_stash(const KArgs &a, const TileLds<WG, 
 // A tile's aggregate never waits on anything, so every walk ends.
 // At least two waves per SIMD (one with 8 records per thread, which cannot
 // fit two): the compiler spills a few registers rather than halve occupancy.
-template <int WG, int ITEMS, typename FT, bool HALO, bool NL>
+template <int WG, int ITEMS, typename FT, bool HALO, bool NL, bool STAG>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ? 1 : 2))) void k_step(const KArgs a)
 {
     constexpr int NW = WG / 64;
@@ -901,7 +996,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ?
         for (int k = 0; k < ITEMS; ++k) {
             d[k] = 0xff;
             if (k * WG + tid < nitems) {
-                advance_one<FT, HALO, NL>(a, X[k], V[k], tau[k], fl);
+                advance_one<FT, HALO, NL, STAG>(a, X[k], V[k], tau[k], fl);
                 d[k] = classify(a.dc, own, X[k], fl);
             }
         }
@@ -956,7 +1051,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ?
 }
 
 // Plain path, steps 1-2: in-place advance of the range's records.
-template <int WG, int ITEMS, typename FT, bool HALO, bool NL>
+template <int WG, int ITEMS, typename FT, bool HALO, bool NL, bool STAG>
 __global__ __launch_bounds__(WG) void k_advance(const KArgs a)
 {
     __shared__ TileHead H;
@@ -990,7 +1085,7 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs a)
         for (int k = 0; k < ITEMS; ++k) {
             const int i = k * WG + tid;
             if (i < nitems) {
-                advance_one<FT, HALO, NL>(a, X[k], V[k], tau[k], fl);
+                advance_one<FT, HALO, NL, STAG>(a, X[k], V[k], tau[k], fl);
                 const int64_t p = first + i;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -1336,7 +1431,7 @@ __global__ __launch_bounds__(256) void k_append(const KArgs a)
         flag_or(hdr, fl);
 }
 
-template <typename FT, bool HALO>
+template <typename FT, bool HALO, bool STAG>
 __global__ __launch_bounds__(256) void k_interp(const KArgs a, int64_t n, const double *x,
                                                 const double *y, const double *z, FT *ux,
                                                 FT *uy, FT *uz)
@@ -1346,7 +1441,7 @@ __global__ __launch_bounds__(256) void k_interp(const KArgs a, int64_t n, const 
          i += (int64_t)gridDim.x * 256) {
         const double X[3] = {x[i], y[i], z[i]};
         FT U[3];
-        interp<FT, HALO>(a.f, X, U, fl);
+        interp<FT, HALO, STAG>(a.f, X, U, fl);
         ux[i] = U[0];
         uy[i] = U[1];
         uz[i] = U[2];
@@ -1373,20 +1468,28 @@ __global__ __launch_bounds__(256) void k_touch(const KArgs a, uint64_t *bits)
                 X[0][c] = a.in.x[c][p];
                 X[1][c] = fma(a.dt, (double)((const FT *)a.in.v[c])[p], X[0][c]);
             }
+            // collocated: one stencil for all components; MAC: one per
+            // component, marked in its own third of the bitmap
+            const int64_t nodes = a.f.sxy * (a.f.n[2] + 2 * a.f.halo);
+            const int ncomp = a.f.stagger ? 3 : 1;
             for (int st = 0; st < 2; ++st) {
-                int c0[3];
-                for (int ax = 0; ax < 3; ++ax)
-                    axis_corner<HALO>(a.f, ax, X[st][ax], c0[ax], fl);
-                for (int cz = 0; cz < 2; ++cz)
-                    for (int cy = 0; cy < 2; ++cy)
-                        for (int cx = 0; cx < 2; ++cx) {
-                            const int ix = cx ? next_corner<HALO>(a.f, 0, c0[0]) : c0[0];
-                            const int iy = cy ? next_corner<HALO>(a.f, 1, c0[1]) : c0[1];
-                            const int iz = cz ? next_corner<HALO>(a.f, 2, c0[2]) : c0[2];
-                            const int64_t node = ix + a.f.sx * iy + a.f.sxy * iz;
-                            atomicOr((unsigned long long *)&bits[node >> 6],
-                                     1ull << (node & 63));
-                        }
+                for (int comp = 0; comp < ncomp; ++comp) {
+                    int c0[3];
+                    for (int ax = 0; ax < 3; ++ax)
+                        axis_corner<HALO>(a.f, ax, X[st][ax],
+                                          a.f.stagger && ax == comp ? 0.0 : 0.5, c0[ax], fl);
+                    for (int cz = 0; cz < 2; ++cz)
+                        for (int cy = 0; cy < 2; ++cy)
+                            for (int cx = 0; cx < 2; ++cx) {
+                                const int ix = cx ? next_corner<HALO>(a.f, 0, c0[0]) : c0[0];
+                                const int iy = cy ? next_corner<HALO>(a.f, 1, c0[1]) : c0[1];
+                                const int iz = cz ? next_corner<HALO>(a.f, 2, c0[2]) : c0[2];
+                                const int64_t node =
+                                    comp * nodes + ix + a.f.sx * iy + a.f.sxy * iz;
+                                atomicOr((unsigned long long *)&bits[node >> 6],
+                                         1ull << (node & 63));
+                            }
+                }
             }
         }
     }
@@ -1422,44 +1525,50 @@ __global__ __launch_bounds__(256) void k_fill(uint64_t *p, int64_t words)
 // variants; Kern<W, I>::step/advance pick the one for the launch.
 template <int W, int I>
 struct Kern {
-    template <typename FT, bool H, bool NL>
+    template <typename FT, bool H, bool NL, bool SG>
     static hipError_t step_t(const KArgs &a, int grid, hipStream_t st)
     {
-        hipLaunchKernelGGL((k_step<W, I, FT, H, NL>), dim3(grid), dim3(W), 0, st, a);
+        hipLaunchKernelGGL((k_step<W, I, FT, H, NL, SG>), dim3(grid), dim3(W), 0, st, a);
         return hipGetLastError();
     }
-    template <typename FT, bool H, bool NL>
+    template <typename FT, bool H, bool NL, bool SG>
     static hipError_t advance_t(const KArgs &a, int grid, hipStream_t st)
     {
-        hipLaunchKernelGGL((k_advance<W, I, FT, H, NL>), dim3(grid), dim3(W), 0, st, a);
+        hipLaunchKernelGGL((k_advance<W, I, FT, H, NL, SG>), dim3(grid), dim3(W), 0, st, a);
         return hipGetLastError();
     }
-    template <typename FT, bool H, bool NL>
+    template <typename FT, bool H, bool NL, bool SG>
     static int occupancy_t()
     {
         int nb = 1;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, FT, H, NL>), W, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, FT, H, NL, SG>),
+                                                           W, 0);
         return nb;
     }
-    template <typename FT>
+    // the halo x drag-law variants of one element type and field arrangement
+    template <typename FT, bool SG>
     static hipError_t step_ft(const KArgs &a, int grid, hipStream_t st)
     {
         const bool h = a.f.halo != 0, nl = a.drag != 0;
-        return h ? (nl ? step_t<FT, true, true>(a, grid, st) : step_t<FT, true, false>(a, grid, st))
-                 : (nl ? step_t<FT, false, true>(a, grid, st) : step_t<FT, false, false>(a, grid, st));
+        return h ? (nl ? step_t<FT, true, true, SG>(a, grid, st)
+                       : step_t<FT, true, false, SG>(a, grid, st))
+                 : (nl ? step_t<FT, false, true, SG>(a, grid, st)
+                       : step_t<FT, false, false, SG>(a, grid, st));
     }
-    template <typename FT>
+    template <typename FT, bool SG>
     static hipError_t advance_ft(const KArgs &a, int grid, hipStream_t st)
     {
         const bool h = a.f.halo != 0, nl = a.drag != 0;
-        return h ? (nl ? advance_t<FT, true, true>(a, grid, st) : advance_t<FT, true, false>(a, grid, st))
-                 : (nl ? advance_t<FT, false, true>(a, grid, st) : advance_t<FT, false, false>(a, grid, st));
+        return h ? (nl ? advance_t<FT, true, true, SG>(a, grid, st)
+                       : advance_t<FT, true, false, SG>(a, grid, st))
+                 : (nl ? advance_t<FT, false, true, SG>(a, grid, st)
+                       : advance_t<FT, false, false, SG>(a, grid, st));
     }
-    template <typename FT>
+    template <typename FT, bool SG>
     static int occupancy_ft(bool h, bool nl)
     {
-        return h ? (nl ? occupancy_t<FT, true, true>() : occupancy_t<FT, true, false>())
-                 : (nl ? occupancy_t<FT, false, true>() : occupancy_t<FT, false, false>());
+        return h ? (nl ? occupancy_t<FT, true, true, SG>() : occupancy_t<FT, true, false, SG>())
+                 : (nl ? occupancy_t<FT, false, true, SG>() : occupancy_t<FT, false, false, SG>());
     }
 };
 

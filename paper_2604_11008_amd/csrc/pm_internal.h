@@ -27,6 +27,7 @@ struct DField {
     const void *u[3];
     int32_t n[3];
     int32_t halo;
+    int32_t stagger; // 0 collocated, 1 MAC (component c face-centred along axis c)
     double r[3];     // n / L per axis
     int64_t sx;      // stored row length (n0 + 2 halo)
     int64_t sxy;     // stored plane size
@@ -118,14 +119,21 @@ hipError_t launch_popcount(const uint64_t *bitmap, int64_t words,
 hipError_t launch_fill(uint64_t *p, int64_t words, hipStream_t st);
 
 // Workgroups per CU that fit for a launch shape of the fused kernel.
-int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear);
-// per element type (pm_step_f64.hip, pm_step_f32.hip)
+int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, bool stagger);
+// per element type (pm_step_f64.hip, pm_step_f32.hip; the MAC variants in
+// pm_mac_f64.hip, pm_mac_f32.hip)
 hipError_t launch_step_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
 hipError_t launch_step_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
 hipError_t launch_advance_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
 hipError_t launch_advance_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
-int step_occupancy_f64(Shape sh, bool halo, bool nonlinear);
-int step_occupancy_f32(Shape sh, bool halo, bool nonlinear);
+int step_occupancy_f64(Shape sh, bool halo, bool nonlinear, bool stagger);
+int step_occupancy_f32(Shape sh, bool halo, bool nonlinear, bool stagger);
+hipError_t launch_step_mac_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
+hipError_t launch_step_mac_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
+hipError_t launch_advance_mac_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
+hipError_t launch_advance_mac_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
+int step_occupancy_mac_f64(Shape sh, bool halo, bool nonlinear);
+int step_occupancy_mac_f32(Shape sh, bool halo, bool nonlinear);
 bool shape_supported(Shape sh);
 
 }  // namespace pm

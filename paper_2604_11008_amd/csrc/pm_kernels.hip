@@ -84,28 +84,34 @@ hipError_t launch_route(const KArgs &a, bool mixed, bool append, hipStream_t st)
     return hipGetLastError();
 }
 
+template <typename FT, bool H, bool SG>
+hipError_t interp_t(const KArgs &a, int grid, int64_t n, const double *x, const double *y,
+                    const double *z, void *ux, void *uy, void *uz, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_interp<FT, H, SG>), dim3(grid), dim3(256), 0, st, a, n, x, y, z,
+                       (FT *)ux, (FT *)uy, (FT *)uz);
+    return hipGetLastError();
+}
+
+template <typename FT>
+hipError_t interp_ft(const KArgs &a, int grid, int64_t n, const double *x, const double *y,
+                     const double *z, void *ux, void *uy, void *uz, hipStream_t st)
+{
+    const bool h = a.f.halo != 0, sg = a.f.stagger != 0;
+    return h ? (sg ? interp_t<FT, true, true>(a, grid, n, x, y, z, ux, uy, uz, st)
+                   : interp_t<FT, true, false>(a, grid, n, x, y, z, ux, uy, uz, st))
+             : (sg ? interp_t<FT, false, true>(a, grid, n, x, y, z, ux, uy, uz, st)
+                   : interp_t<FT, false, false>(a, grid, n, x, y, z, ux, uy, uz, st));
+}
+
 hipError_t launch_interp(const KArgs &a, bool mixed, int64_t n, const double *x,
                          const double *y, const double *z, void *ux, void *uy, void *uz,
                          hipStream_t st)
 {
     int64_t g = (n + 255) / 256;
     const int grid = (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
-    if (mixed) {
-        if (a.f.halo)
-            hipLaunchKernelGGL((k_interp<float, true>), dim3(grid), dim3(256), 0, st, a, n, x,
-                               y, z, (float *)ux, (float *)uy, (float *)uz);
-        else
-            hipLaunchKernelGGL((k_interp<float, false>), dim3(grid), dim3(256), 0, st, a, n, x,
-                               y, z, (float *)ux, (float *)uy, (float *)uz);
-    } else {
-        if (a.f.halo)
-            hipLaunchKernelGGL((k_interp<double, true>), dim3(grid), dim3(256), 0, st, a, n,
-                               x, y, z, (double *)ux, (double *)uy, (double *)uz);
-        else
-            hipLaunchKernelGGL((k_interp<double, false>), dim3(grid), dim3(256), 0, st, a, n,
-                               x, y, z, (double *)ux, (double *)uy, (double *)uz);
-    }
-    return hipGetLastError();
+    return mixed ? interp_ft<float>(a, grid, n, x, y, z, ux, uy, uz, st)
+                 : interp_ft<double>(a, grid, n, x, y, z, ux, uy, uz, st);
 }
 
 hipError_t launch_touch(const KArgs &a, bool mixed, uint64_t *bits, hipStream_t st)
@@ -150,10 +156,10 @@ hipError_t launch_advance(const KArgs &a, Shape sh, bool mixed, int grid, hipStr
     return mixed ? launch_advance_f32(a, sh, grid, st) : launch_advance_f64(a, sh, grid, st);
 }
 
-int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear)
+int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, bool stagger)
 {
-    const int nb = mixed ? step_occupancy_f32(sh, halo, nonlinear)
-                         : step_occupancy_f64(sh, halo, nonlinear);
+    const int nb = mixed ? step_occupancy_f32(sh, halo, nonlinear, stagger)
+                         : step_occupancy_f64(sh, halo, nonlinear, stagger);
     return nb < 1 ? 1 : nb;
 }
 

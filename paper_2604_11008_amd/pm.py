@@ -32,7 +32,7 @@ class PMError(RuntimeError):
 
 class _Field(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("halo", C.c_int32), ("L", C.c_double * 3),
-                ("dtype", C.c_int32), ("pad_", C.c_int32), ("u", C.c_void_p * 3)]
+                ("dtype", C.c_int32), ("stagger", C.c_int32), ("u", C.c_void_p * 3)]
 
 
 class _Decomp(C.Structure):
@@ -122,9 +122,10 @@ def _p(t: torch.Tensor):
 # --- device-side objects -------------------------------------------------------------
 
 class DeviceField:
-    """Velocity field on the device: three flat tensors (float64 or float32)."""
+    """Velocity field on the device: three flat tensors (float64 or float32);
+    stagger=True: MAC arrangement (component c on the faces normal to axis c)."""
 
-    def __init__(self, u, n, halo, L, device="cuda"):
+    def __init__(self, u, n, halo, L, device="cuda", stagger=False):
         self.u = [torch.as_tensor(np.ascontiguousarray(c).reshape(-1)).to(device)
                   if not isinstance(c, torch.Tensor) else c.reshape(-1).contiguous()
                   for c in u]
@@ -138,8 +139,9 @@ class DeviceField:
         if any(c.numel() != st[0] * st[1] * st[2] for c in self.u):
             raise PMError("field size does not match n and halo")
         self.dtype = F64 if dt == torch.float64 else F32
+        self.stagger = int(bool(stagger))
         self.c = _Field((C.c_int32 * 3)(*self.n), self.halo, (C.c_double * 3)(*self.L),
-                        self.dtype, 0, (C.c_void_p * 3)(*[_p(c) for c in self.u]))
+                        self.dtype, self.stagger, (C.c_void_p * 3)(*[_p(c) for c in self.u]))
 
     @property
     def mixed(self):
@@ -392,7 +394,7 @@ class Context:
     def touched_nodes(self, field, pin, params, stream=None):
         pc = self._pool(pin, "in")
         nodes = (field.n[0] + 2 * field.halo) * (field.n[1] + 2 * field.halo) * \
-            (field.n[2] + 2 * field.halo)
+            (field.n[2] + 2 * field.halo) * (3 if field.stagger else 1)
         words = (nodes + 63) // 64
         bm = torch.empty(words, dtype=torch.int64, device=field.u[0].device)
         out = C.c_int64(0)

@@ -25,7 +25,8 @@ from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 SOURCES = [os.path.join(PKG, "csrc", f) for f in ("pm_device.h", "pm_step_f64.hip",
-                                                    "pm_step_f32.hip", "pm_kernels.hip",
+                                                    "pm_step_f32.hip", "pm_mac_f64.hip",
+                                                    "pm_mac_f32.hip", "pm_kernels.hip",
                                                     "pm_internal.h")]
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 1 << 30

@@ -25,8 +25,9 @@ class Case:
 
     def __init__(self, name, npart=None, n=None, p=None, order="canonical", mode=None,
                  face=0.1, edge=0.03, corner=0.02, dt_scale=1.0, slack=0.05, extra=1024,
-                 drag="stokes"):
-        say(f"[case] {name} np={npart} n={n} p={p} order={order} mode={mode} drag={drag}")
+                 drag="stokes", stagger=False):
+        say(f"[case] {name} np={npart} n={n} p={p} order={order} mode={mode} drag={drag} "
+            f"stagger={stagger}")
         self.drag = drag
         self.wl = gen.make_workload(name, np_override=npart, n_override=n, p_override=p,
                                     order=order, slack=slack, extra=extra)
@@ -35,7 +36,8 @@ class Case:
         self.dt = wl.dt * dt_scale
         self.g = wl.g
         self.fh = wl.stored_field(np.float64)
-        self.ofield = oracle.Field(self.fh, wl.n, wl.halo, wl.L)
+        # a MAC case reads the same arrays as staggered components
+        self.ofield = oracle.Field(self.fh, wl.n, wl.halo, wl.L, stagger=stagger)
         self.odc = oracle.Decomp(wl.p, wl.bounds)
         U, _ = oracle.interp(self.ofield, wl.pool.x)
         if self.mode == "mixed":
@@ -48,7 +50,8 @@ class Case:
         self.dev = torch.device("cuda:0")
         fdev = [np.asarray(u, dtype=np.float32) for u in self.fh] if self.mode == "mixed" \
             else self.fh
-        self.field = pm.DeviceField(fdev, wl.n, wl.halo, wl.L, device=self.dev)
+        self.field = pm.DeviceField(fdev, wl.n, wl.halo, wl.L, device=self.dev,
+                                    stagger=stagger)
         self.dc = pm.Decomp(wl.p, wl.bounds)
         self.sb, self.sc = gen.send_layout(wl.pool.count, face=face, edge=edge, corner=corner)
         self.params = pm.Params(self.dt, self.g, drag=drag)

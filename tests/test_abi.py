@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def header_layout(tmp_path):
     """sizeof and field offsets of the header's structs, from a C compiler."""
     probes = {
-        "pm_field": ["n", "halo", "L", "dtype", "u"],
+        "pm_field": ["n", "halo", "L", "dtype", "stagger", "u"],
         "pm_decomp": ["p", "bounds"],
         "pm_particles": ["nsub", "vdtype", "base", "cap", "count", "x", "v", "tau", "id"],
         "pm_sendbufs": ["base", "cap", "count", "x", "v", "tau", "id"],
