@@ -240,8 +240,9 @@ def main():
         achieved = alg["fused_kernel"] / (k_ms * 1e-3) / 1e9
         from paper_2604_11008_amd import profsum
         wg, items, _ = ctx.get_tuning()
+        tf = lambda b: "true" if b else "false"  # noqa: E731
         variant = (f"k_step<{wg}, {items}, {'float' if mixed else 'double'}, "
-                   f"{'true' if wl.halo else 'false'}>")
+                   f"{tf(wl.halo)}, {tf(args.drag == 'nonlinear')}, {tf(args.stagger)}>")
         tpath = args.traffic or os.path.join(ROOT, "profiles",
                                              f"k_step_{args.config}_traffic.json")
         traffic = None
