@@ -349,19 +349,30 @@ def morton3(i, j, k, bits=11):
     return code
 
 
+def cell_key(i, j, k):
+    """Sort key of the canonical order: the Z-order code of (i/2, j, k), then
+    the parity of i, so that the smallest blocks are two cells long in x,
+    the axis along which a stencil's two nodes share memory sectors."""
+    i = np.asarray(i, dtype=np.int64)
+    return morton3(i >> 1, j, k) * 2 + (i & 1)
+
+
 def build_pool(pos, tau, ids, p, bnds, n, L=TWO_PI, slack=0.05, extra=1024,
                vdtype=np.float64, order="canonical", shuffle_seed=None):
     """Pool with each particle in its owner's segment.  Canonical order: by
-    subdomain, then the Z-order (Morton) code of the cell, then id.
-    order="rowmajor" sorts by cell (z, y, x) instead; order="shuffled"
-    permutes each segment of the canonical order with the shuffle seed."""
+    subdomain, then cell_key of the cell, then id.  order="morton" uses the
+    plain Z-order code of the cell, order="rowmajor" the cell (z, y, x);
+    order="shuffled" permutes each segment of the canonical order with the
+    shuffle seed."""
     nsub = p[0] * p[1] * p[2]
     s = owner(pos, bnds, p)
     cell = [np.clip(np.floor(pos[a] * (n / L)).astype(np.int64), 0, n - 1) for a in range(3)]
     if order == "rowmajor":
         perm = np.lexsort((ids, cell[0], cell[1], cell[2], s))
-    else:
+    elif order == "morton":
         perm = np.lexsort((ids, morton3(cell[0], cell[1], cell[2]), s))
+    else:
+        perm = np.lexsort((ids, cell_key(cell[0], cell[1], cell[2]), s))
     s_sorted = s[perm]
     counts = np.bincount(s_sorted, minlength=nsub).astype(np.int64)
     if order == "shuffled":

@@ -5,8 +5,9 @@ Traffic of a kernel = FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two
 separate `rocprofv3 --pmc` runs, each scaled by what the same counter reads
 for a plain device copy of known size in the same run (bench.py
 --copy-probe: torch copy of 1 GiB, i.e. 1 GiB read and 1 GiB written).  The
-record carries a hash of the kernel sources; once they change, the record no
-longer applies and bench.py reports traffic as null.
+record carries a hash of the kernel sources and of the workload generator;
+once either changes, the record no longer applies and bench.py reports
+traffic as null.
 
 Usage (after the rocprofv3 runs):
   python -m paper_2604_11008_amd.profsum stats  <kernel_stats.csv>
@@ -24,10 +25,12 @@ import sys
 from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
+# the kernel sources and the workload generator (the traffic depends on both)
 SOURCES = [os.path.join(PKG, "csrc", f) for f in ("pm_device.h", "pm_step_f64.hip",
                                                     "pm_step_f32.hip", "pm_mac_f64.hip",
                                                     "pm_mac_f32.hip", "pm_kernels.hip",
-                                                    "pm_internal.h")]
+                                                    "pm_internal.h")] + \
+    [os.path.join(PKG, "gen.py")]
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 1 << 30
 

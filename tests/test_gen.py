@@ -60,8 +60,21 @@ def test_pool_layout_and_canonical_order():
         assert np.all((x >= 0) & (x < wl.L))
         np.testing.assert_array_equal(gen.owner(x, wl.bounds, wl.p), s)
         cell = np.floor(x * (wl.n / wl.L)).astype(np.int64)
-        key = gen.morton3(cell[0], cell[1], cell[2])
+        key = gen.cell_key(cell[0], cell[1], cell[2])
         assert np.all(np.diff(key) >= 0)
+
+
+def test_cell_key_orders_x_pairs_then_z_order():
+    i, j, k = np.meshgrid(np.arange(4), np.arange(2), np.arange(2), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+    order = np.argsort(gen.cell_key(i, j, k), kind="stable")
+    cells = list(zip(i[order], j[order], k[order]))
+    # x pairs are the leaves; the pairs themselves follow the Z-order of
+    # (i/2, j, k): x pair 0, x pair 1, then j, then k
+    assert cells[:4] == [(0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 0, 0)]
+    assert cells[4:8] == [(0, 1, 0), (1, 1, 0), (2, 1, 0), (3, 1, 0)]
+    assert cells[8:10] == [(0, 0, 1), (1, 0, 1)]
+    assert len(set(gen.cell_key(i, j, k))) == i.size
 
 
 def test_blob_and_lognormal_distributions():
