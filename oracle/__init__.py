@@ -57,6 +57,8 @@ def lib():
         L.orc_append.restype = C.c_uint
         L.orc_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.orc_step.restype = C.c_uint
+        L.orc_step_staged.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_step_staged.restype = C.c_uint
         _lib = L
     return _lib
 
@@ -75,6 +77,13 @@ class _Decomp(C.Structure):
 class _Pool(C.Structure):
     _fields_ = [("nseg", C.c_int), ("base", C.c_void_p), ("cap", C.c_void_p),
                 ("count", C.c_void_p), ("x", C.c_void_p * 3), ("v", C.c_void_p * 3),
+                ("tau", C.c_void_p), ("id", C.c_void_p)]
+
+
+class _XPool(C.Structure):
+    _fields_ = [("nseg", C.c_int), ("base", C.c_void_p), ("cap", C.c_void_p),
+                ("count", C.c_void_p), ("x", C.c_void_p * 3), ("v", C.c_void_p * 3),
+                ("xs", C.c_void_p * 3), ("vs", C.c_void_p * 3), ("a", C.c_void_p * 3),
                 ("tau", C.c_void_p), ("id", C.c_void_p)]
 
 
@@ -167,6 +176,39 @@ class _PoolView:
                 dst[...] = src.astype(dst.dtype)
 
 
+class _XPoolView:
+    """float64 copies of a stage pool's arrays (gen.StagePool), the C struct,
+    and write_back() into the original."""
+
+    NAMES = ("x", "v", "xs", "vs", "a")
+
+    def __init__(self, pool):
+        self.pool = pool
+        for n in self.NAMES:
+            setattr(self, n, _f64(getattr(pool, n)))
+        self.tau = _f64(pool.tau)
+        self.id = np.ascontiguousarray(pool.id, dtype=np.uint64)
+        self.base = np.ascontiguousarray(pool.base, dtype=np.int64)
+        self.cap = np.ascontiguousarray(pool.cap, dtype=np.int64)
+        self.count = np.ascontiguousarray(pool.count, dtype=np.int64)
+        arr = lambda n: (C.c_void_p * 3)(*[getattr(self, n)[a].ctypes.data for a in range(3)])  # noqa: E731
+        self._c = _XPool(len(self.base), self.base.ctypes.data, self.cap.ctypes.data,
+                         self.count.ctypes.data, arr("x"), arr("v"), arr("xs"), arr("vs"),
+                         arr("a"), self.tau.ctypes.data, self.id.ctypes.data)
+
+    @property
+    def ref(self):
+        return C.byref(self._c)
+
+    def write_back(self):
+        p = self.pool
+        for name in self.NAMES + ("tau", "id", "count"):
+            dst = getattr(p, name)
+            src = getattr(self, name)
+            if dst is not src:
+                dst[...] = src.astype(dst.dtype)
+
+
 # --- the calls -----------------------------------------------------------------
 
 def interp(field: Field, X):
@@ -246,3 +288,18 @@ def step(field: Field, decomp: Decomp, dt, g, pin, pout, send, drag="stokes", nu
     vout.write_back()
     vsend.write_back()
     return stay, int(flags)
+
+
+def step_staged(field: Field, decomp: Decomp, dt, g, pin, mid, mid_send, pout, send,
+                drag="stokes", nu=1.5e-5, density_ratio=843.0):
+    """Whole step with migration after each RK2 stage: pin -> mid (stage-1
+    records, leavers through mid_send; gen.StagePool) -> pout (leavers through
+    send).  pin is unchanged.  Returns the flags."""
+    vin, vout, vsend = _PoolView(pin), _PoolView(pout), _PoolView(send)
+    vmid, vms = _XPoolView(mid), _XPoolView(mid_send)
+    pr = _params(dt, g, drag, nu, density_ratio)
+    flags = lib().orc_step_staged(field.ref, decomp.ref, C.byref(pr), vin.ref, vmid.ref,
+                                  vms.ref, vout.ref, vsend.ref)
+    for v in (vmid, vms, vout, vsend):
+        v.write_back()
+    return int(flags)

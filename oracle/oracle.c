@@ -440,3 +440,181 @@ unsigned orc_step(const orc_field *f, const orc_decomp *dc,
     free(mem);
     return flags;
 }
+
+/* ------------------------------------------------------------------ */
+/* Per-stage migration (Sect. 3.2.2: the particle arrays are exchanged  */
+/* after each RK2 stage).  The partition and append above give every    */
+/* record's destination; a record's index travels in the id field of a */
+/* carrier pool and picks up the other arrays afterwards.               */
+/* ------------------------------------------------------------------ */
+
+static int64_t pool_extent(int nseg, const int64_t *base, const int64_t *cap)
+{
+    int64_t e = 0;
+    for (int s = 0; s < nseg; ++s)
+        if (base[s] + cap[s] > e)
+            e = base[s] + cap[s];
+    return e > 0 ? e : 1;
+}
+
+/* A carrier pool over the segments of (base, cap, count): x, v, tau, id
+ * arrays of `extent` records in one allocation. */
+static double *carrier(orc_pool *c, int nseg, const int64_t *base, const int64_t *cap,
+                       int64_t *count, int64_t extent)
+{
+    double *mem = (double *)calloc((size_t)extent * 8, sizeof(double));
+    if (!mem)
+        abort();
+    c->nseg = nseg;
+    c->base = base;
+    c->cap = cap;
+    c->count = count;
+    for (int a = 0; a < 3; ++a) {
+        c->x[a] = mem + (size_t)a * (size_t)extent;
+        c->v[a] = mem + (size_t)(3 + a) * (size_t)extent;
+    }
+    c->tau = mem + (size_t)6 * (size_t)extent;
+    c->id = (uint64_t *)(mem + (size_t)7 * (size_t)extent);
+    return mem;
+}
+
+/* X_n of record p (owned by subdomain s, sent in direction d) in the
+ * receiver's periodic image: -L leaving through L, +L leaving through 0. */
+static void shift_xn(const orc_decomp *dc, int s, int d, const double X[3], double Xo[3])
+{
+    const int own[3] = {s % dc->p[0], (s / dc->p[0]) % dc->p[1], s / (dc->p[0] * dc->p[1])};
+    const int o[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+    for (int a = 0; a < 3; ++a) {
+        const double L = dc->b[a][dc->p[a]];
+        Xo[a] = X[a];
+        if (o[a] > 0 && own[a] == dc->p[a] - 1)
+            Xo[a] = X[a] - L;
+        else if (o[a] < 0 && own[a] == 0)
+            Xo[a] = X[a] + L;
+    }
+}
+
+/* Expand carrier record r (whose id is the source index p) into xp[at]. */
+static void expand(orc_xpool *xp, int64_t at, const orc_pool *c, int64_t r, const orc_pool *in,
+                   const double *acc, const int *seg_of, const int32_t *dir,
+                   const orc_decomp *dc)
+{
+    const int64_t p = (int64_t)c->id[r];
+    const double X[3] = {in->x[0][p], in->x[1][p], in->x[2][p]};
+    double Xo[3];
+    shift_xn(dc, seg_of[p], dir[p], X, Xo);
+    for (int a = 0; a < 3; ++a) {
+        xp->x[a][at] = Xo[a];
+        xp->v[a][at] = in->v[a][p];
+        xp->xs[a][at] = c->x[a][r];
+        xp->vs[a][at] = c->v[a][r];
+        xp->a[a][at] = acc[(size_t)p * 3 + a];
+    }
+    xp->tau[at] = in->tau[p];
+    xp->id[at] = in->id[p];
+}
+
+unsigned orc_step_staged(const orc_field *f, const orc_decomp *dc,
+                         const orc_params *pr, const orc_pool *in, orc_xpool *mid,
+                         orc_xpool *mid_send, orc_pool *out, orc_pool *send)
+{
+    unsigned flags = 0;
+    const double dt = pr->dt;
+    const double half_dt = 0.5 * dt;
+    const int nsub = in->nseg;
+    const int64_t ext_in = pool_extent(nsub, in->base, in->cap);
+    const int64_t ext_mid = pool_extent(mid->nseg, mid->base, mid->cap);
+    const int64_t ext_ms = pool_extent(nsub * 27, mid_send->base, mid_send->cap);
+    int64_t *stay = (int64_t *)calloc((size_t)(nsub > 0 ? nsub : 1), sizeof(int64_t));
+    int32_t *dir = (int32_t *)calloc((size_t)ext_in, sizeof(int32_t));
+    int *seg_of = (int *)calloc((size_t)ext_in, sizeof(int));
+    double *acc = (double *)calloc((size_t)ext_in * 3, sizeof(double));
+    int64_t *cnt_in = (int64_t *)calloc((size_t)(nsub > 0 ? nsub : 1), sizeof(int64_t));
+    if (!stay || !dir || !seg_of || !acc || !cnt_in)
+        abort();
+
+    /* stage 1 into a carrier pool: x = X*, v = V*, id = record index */
+    orc_pool c1, cm, cs;
+    for (int s = 0; s < nsub; ++s)
+        cnt_in[s] = in->count[s];
+    double *m1 = carrier(&c1, nsub, in->base, in->cap, cnt_in, ext_in);
+    for (int s = 0; s < nsub; ++s) {
+        for (int64_t i = 0; i < in->count[s]; ++i) {
+            const int64_t p = in->base[s] + i;
+            const double t = in->tau[p];
+            double X[3], V[3], U1[3], s1[3];
+            for (int a = 0; a < 3; ++a) {
+                X[a] = in->x[a][p];
+                V[a] = in->v[a][p];
+            }
+            flags |= orc_interp(f, X, U1);
+            for (int a = 0; a < 3; ++a)
+                s1[a] = U1[a] - V[a];
+            const double f1 = drag_factor(pr, t, s1);
+            for (int a = 0; a < 3; ++a) {
+                const double A1 = f1 * s1[a] / t + pr->g[a];
+                acc[(size_t)p * 3 + a] = A1;
+                c1.x[a][p] = X[a] + dt * V[a];
+                c1.v[a][p] = V[a] + dt * A1;
+            }
+            c1.tau[p] = t;
+            c1.id[p] = (uint64_t)p;
+            seg_of[p] = s;
+        }
+    }
+    int64_t *cnt_mid = mid->count;
+    double *mm = carrier(&cm, mid->nseg, mid->base, mid->cap, cnt_mid, ext_mid);
+    double *ms = carrier(&cs, nsub * 27, mid_send->base, mid_send->cap, mid_send->count, ext_ms);
+    flags |= orc_partition(dc, &c1, &cm, &cs, stay, dir, NULL);
+    flags |= orc_append(dc, &cs, stay, &cm);
+    for (int t = 0; t < mid->nseg; ++t)
+        for (int64_t k = 0; k < mid->count[t] && k < mid->cap[t]; ++k)
+            expand(mid, mid->base[t] + k, &cm, mid->base[t] + k, in, acc, seg_of, dir, dc);
+    for (int q = 0; q < nsub * 27; ++q)
+        for (int64_t k = 0; k < mid_send->count[q] && k < mid_send->cap[q]; ++k)
+            expand(mid_send, mid_send->base[q] + k, &cs, mid_send->base[q] + k, in, acc,
+                   seg_of, dir, dc);
+
+    /* stage 2 in the new owners, into a carrier pool of the final state */
+    orc_pool c2;
+    int64_t *cnt2 = (int64_t *)calloc((size_t)(mid->nseg > 0 ? mid->nseg : 1), sizeof(int64_t));
+    if (!cnt2)
+        abort();
+    for (int t = 0; t < mid->nseg; ++t)
+        cnt2[t] = mid->count[t] < mid->cap[t] ? mid->count[t] : mid->cap[t];
+    double *m2 = carrier(&c2, mid->nseg, mid->base, mid->cap, cnt2, ext_mid);
+    for (int t = 0; t < mid->nseg; ++t) {
+        for (int64_t k = 0; k < cnt2[t]; ++k) {
+            const int64_t r = mid->base[t] + k;
+            const double tt = mid->tau[r];
+            double Xs[3], U2[3], s2[3];
+            for (int a = 0; a < 3; ++a)
+                Xs[a] = mid->xs[a][r];
+            flags |= orc_interp(f, Xs, U2);
+            for (int a = 0; a < 3; ++a)
+                s2[a] = U2[a] - mid->vs[a][r];
+            const double f2 = drag_factor(pr, tt, s2);
+            for (int a = 0; a < 3; ++a) {
+                const double A2 = f2 * s2[a] / tt + pr->g[a];
+                c2.x[a][r] = mid->x[a][r] + half_dt * (mid->v[a][r] + mid->vs[a][r]);
+                c2.v[a][r] = mid->v[a][r] + half_dt * (mid->a[a][r] + A2);
+            }
+            c2.tau[r] = tt;
+            c2.id[r] = mid->id[r];
+        }
+    }
+    flags |= orc_partition(dc, &c2, out, send, stay, NULL, NULL);
+    flags |= orc_append(dc, send, stay, out);
+
+    free(m1);
+    free(mm);
+    free(ms);
+    free(m2);
+    free(cnt2);
+    free(cnt_in);
+    free(acc);
+    free(seg_of);
+    free(dir);
+    free(stay);
+    return flags;
+}

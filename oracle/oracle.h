@@ -138,6 +138,31 @@ unsigned orc_step(const orc_field *f, const orc_decomp *dc,
                   const orc_params *pr, const orc_pool *in, orc_pool *out,
                   orc_pool *send, int64_t *stay_count);
 
+/* Mid-step records of per-stage migration (the paper migrates after each
+ * RK2 stage, Sect. 3.2.2): X_n, V_n, the stage-1 position and velocity X*,
+ * V*, and the stage-1 acceleration a = dV/dt, plus tau and id: 17 values,
+ * the paper's 17 arrays with tau standing for the diameter. */
+typedef struct {
+    int nseg;
+    const int64_t *base;
+    const int64_t *cap;
+    int64_t *count;
+    double *x[3], *v[3], *xs[3], *vs[3], *a[3];
+    double *tau;
+    uint64_t *id;
+} orc_xpool;
+
+/* Whole step with migration after each RK2 stage.  Stage 1: X*, V* and a
+ * from X_n, V_n; every particle is classified by X* and migrated with its 17
+ * values to `mid` (leavers through `mid_send`); X_n moves into the
+ * receiver's periodic image by the same +-L as X* (plain arithmetic).
+ * Stage 2 in the new owner: X' = X_n + dt/2 (V_n + V*), V' = V_n + dt/2 (a +
+ * a(X*, V*)); classified by X' and migrated to `out` (leavers through
+ * `send`).  `in` is unchanged. */
+unsigned orc_step_staged(const orc_field *f, const orc_decomp *dc,
+                         const orc_params *pr, const orc_pool *in, orc_xpool *mid,
+                         orc_xpool *mid_send, orc_pool *out, orc_pool *send);
+
 #ifdef __cplusplus
 }
 #endif

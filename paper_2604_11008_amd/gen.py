@@ -295,6 +295,41 @@ def empty_pool(base, cap, vdtype=np.float64):
                 base=base, cap=cap, count=np.zeros(len(base), dtype=np.int64))
 
 
+@dataclass
+class StagePool:
+    """Mid-step records of per-stage migration: X_n, V_n, X*, V*, the stage-1
+    acceleration a, tau and id (structure of arrays, per-segment slices)."""
+    x: np.ndarray            # (3, size) float64
+    v: np.ndarray            # (3, size) float64 or float32
+    xs: np.ndarray           # (3, size) float64
+    vs: np.ndarray           # (3, size) like v
+    a: np.ndarray            # (3, size) like v
+    tau: np.ndarray
+    id: np.ndarray
+    base: np.ndarray
+    cap: np.ndarray
+    count: np.ndarray
+
+    @property
+    def size(self):
+        return self.x.shape[1]
+
+    def segment(self, q):
+        b, c = int(self.base[q]), int(self.count[q])
+        return slice(b, b + c)
+
+
+def empty_stage_pool(base, cap, vdtype=np.float64):
+    base = np.asarray(base, dtype=np.int64)
+    cap = np.asarray(cap, dtype=np.int64)
+    size = max(int((base + cap).max()) if len(base) else 0, 1)
+    z = lambda dt: np.zeros((3, size), dtype=dt)  # noqa: E731
+    return StagePool(x=z(np.float64), v=z(vdtype), xs=z(np.float64), vs=z(vdtype),
+                     a=z(vdtype), tau=np.zeros(size, dtype=vdtype),
+                     id=np.zeros(size, dtype=np.uint64), base=base, cap=cap,
+                     count=np.zeros(len(base), dtype=np.int64))
+
+
 def neighbour_max(counts, p):
     """Largest count among the 26 periodic neighbours of every subdomain."""
     c = np.asarray(counts).reshape(p[2], p[1], p[0])
