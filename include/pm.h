@@ -156,6 +156,41 @@ typedef enum {
                               r from tau = (2/9)(rho_p/rho) r^2 / nu           */
 } pm_drag;
 
+/* Mid-step records of per-stage migration (the paper exchanges the particle
+ * arrays after each RK2 stage, Sect. 3.2.2): X_n (x), V_n (v), the stage-1
+ * position X* (xs) and velocity V* (vs) and acceleration dV/dt (a), tau and
+ * id -- 17 values, 136 bytes in FP64, the paper's 17 arrays with tau in
+ * place of the diameter.  Segments as in pm_particles; x and xs float64,
+ * the rest of type vdtype. */
+typedef struct {
+    int32_t nsub;
+    int32_t vdtype;     /* pm_dtype */
+    const int64_t *base;
+    const int64_t *cap;
+    int64_t *count;
+    double *x[3];
+    void *v[3];
+    double *xs[3];
+    void *vs[3];
+    void *a[3];
+    void *tau;
+    uint64_t *id;
+} pm_stage_particles;
+
+/* Send buffers of the stage-1 exchange: segment s*27+d, mid-step records. */
+typedef struct {
+    const int64_t *base;   /* device [nsub*27] */
+    const int64_t *cap;    /* device [nsub*27] */
+    int64_t *count;        /* device [nsub*27], written */
+    double *x[3];
+    void *v[3];
+    double *xs[3];
+    void *vs[3];
+    void *a[3];
+    void *tau;
+    uint64_t *id;
+} pm_stage_sendbufs;
+
 /* Time step, constant body force (gravity) added to dV/dt, and the drag law.
  * nu (kinematic viscosity) and density_ratio (rho_p/rho) are read only for
  * PM_DRAG_NONLINEAR, in the units of the field, the box and tau; both must
@@ -275,6 +310,22 @@ pm_status pm_set_graph(pm_ctx *ctx, int32_t enable);
 pm_status pm_set_timing(pm_ctx *ctx, int32_t max_records);
 pm_status pm_kernel_times(pm_ctx *ctx, int32_t *n, double *total_ms, float *ms,
                           int32_t max_ms);
+
+/* The step with migration after each RK2 stage, as the paper does it
+ * (Sect. 3.2.2): stage 1 (X* = X_n + dt V_n, V* = V_n + dt a) for every
+ * particle of `in`, which is then classified by X* and exchanged with its
+ * 17 values into `mid` (leavers through `mid_send`; X_n is moved into the
+ * receiver's periodic image by the same +-L as X*, in plain arithmetic);
+ * stage 2 in the new owner (X' = X_n + dt/2 (V_n + V*), V' = V_n + dt/2 (a
+ * + a(X*, V*))), classified by X' and exchanged into `out` (leavers through
+ * `send`).  Each exchange is the same scan, pack, compact and append as
+ * pm_step's.  Collocated fields only; `in` is unchanged; mid must fit the
+ * context's pool extent and mid_send its send extent.  Launch shapes with
+ * at most 1024 records per tile (default 256 x 2). */
+pm_status pm_step_staged(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
+                         const pm_particles *in, pm_stage_particles *mid,
+                         pm_stage_sendbufs *mid_send, pm_particles *out,
+                         pm_sendbufs *send, const pm_params *params, void *stream);
 
 /* Untimed diagnostic: number of distinct field nodes read by the stage-1
  * and stage-2 stencils of one pm_step from `in` (an exact count, through a

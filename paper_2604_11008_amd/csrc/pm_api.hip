@@ -75,7 +75,8 @@ WsLayout ws_layout(int64_t pool_extent, int64_t send_extent, int32_t nsub)
     // every segment's staging area is rounded up to a multiple of 16 records
     L.stg_extent = send_extent + 16 * (int64_t)ns + 16;
     L.stg = o;
-    o += 8 * align256((size_t)L.stg_extent * 8) + align256((size_t)L.stg_extent);
+    // x, v, tau, id, and the mid-step fields xs, vs, a of per-stage migration
+    o += 17 * align256((size_t)L.stg_extent * 8) + align256((size_t)L.stg_extent);
     L.total = o;
     return L;
 }
@@ -219,6 +220,32 @@ pm_status conv_send(const pm_sendbufs *s, pm::DPool &d)
     }
     d.tau = s->tau;
     d.id = s->id;
+    return PM_OK;
+}
+
+// The mid-step pools of per-stage migration: the plain fields plus xs, vs, a.
+template <typename P>
+pm_status conv_stage(const P *p, const char *name, pm::DPool &d)
+{
+    if (!p)
+        return arg_error("%s is NULL", name);
+    if (!p->base || !p->cap || !p->count || !p->tau || !p->id)
+        return arg_error("%s has a NULL array", name);
+    for (int a = 0; a < 3; ++a)
+        if (!p->x[a] || !p->v[a] || !p->xs[a] || !p->vs[a] || !p->a[a])
+            return arg_error("%s has a NULL array", name);
+    d.base = p->base;
+    d.cap = p->cap;
+    d.count = p->count;
+    for (int a = 0; a < 3; ++a) {
+        d.x[a] = p->x[a];
+        d.v[a] = p->v[a];
+        d.xs[a] = p->xs[a];
+        d.vs[a] = p->vs[a];
+        d.a[a] = p->a[a];
+    }
+    d.tau = p->tau;
+    d.id = p->id;
     return PM_OK;
 }
 
@@ -376,7 +403,12 @@ pm_status pm_create(pm_ctx **out, void *workspace, size_t ws_bytes, int64_t pool
     }
     ctx->ws.stg_tau = (double *)(g + 6 * fs);
     ctx->ws.stg_id = (uint64_t *)(g + 7 * fs);
-    ctx->ws.stg_d = (uint8_t *)(g + 8 * fs);
+    for (int c = 0; c < 3; ++c) {
+        ctx->ws.stg_xs[c] = (double *)(g + (8 + c) * fs);
+        ctx->ws.stg_vs[c] = (double *)(g + (11 + c) * fs);
+        ctx->ws.stg_a[c] = (double *)(g + (14 + c) * fs);
+    }
+    ctx->ws.stg_d = (uint8_t *)(g + 17 * fs);
     ctx->ws.max_tiles = L.max_tiles;
     ctx->ws.pool_extent = pool_extent;
     ctx->ws.send_extent = send_extent;
@@ -577,6 +609,76 @@ static pm_status step_args(pm_ctx *ctx, const pm_field *field, const pm_decomp *
     k.sub_first = 0;
     k.sub_count = in->nsub;
     return PM_OK;
+}
+
+// One stage of per-stage migration: prep, the stage's fused kernel, and the
+// exchange (mid-step records after stage 1, plain ones after stage 2).
+static pm_status queue_stage(pm_ctx *ctx, pm::KArgs &k, bool mixed, int stage, pm::Shape sh,
+                             hipStream_t st, bool timed)
+{
+    k.tile = sh.wg * sh.items;
+    k.cpt = append_cpt(k.sub_count);
+    PM_HIP(pm::launch_prep(k,
+                           pm::kPrepTiles | pm::kPrepStaging | pm::kPrepZeroLb |
+                               pm::kPrepZeroCounts | pm::kPrepCheckIn | pm::kPrepCheckOut |
+                               pm::kPrepCheckSend,
+                           st),
+           "prep launch");
+    const int per = ctx->blocks_per_cu > 0
+                        ? ctx->blocks_per_cu
+                        : pm::stage_occupancy(sh, mixed, k.f.halo != 0, k.drag != 0, stage);
+    if (timed)
+        PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount], st), "event record");
+    PM_HIP(pm::launch_stage(k, sh, mixed, stage, std::max(1, ctx->cus * per), st),
+           "stage launch");
+    if (timed) {
+        PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount + 1], st), "event record");
+        ctx->tcount++;
+    }
+    PM_HIP(pm::launch_route(k, mixed, true, st, stage == 1), "route launch");
+    return PM_OK;
+}
+
+pm_status pm_step_staged(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
+                         const pm_particles *in, pm_stage_particles *mid,
+                         pm_stage_sendbufs *mid_send, pm_particles *out, pm_sendbufs *send,
+                         const pm_params *params, void *stream)
+{
+    pm::KArgs k;
+    bool mixed = false;
+    pm_status s = step_args(ctx, field, decomp, in, out, send, params, k, mixed);
+    if (s)
+        return s;
+    if (field->stagger)
+        return arg_error("per-stage migration takes a collocated field");
+    pm::DPool dmid{}, dms{};
+    s = conv_stage(mid, "mid", dmid);
+    if (!s)
+        s = conv_stage(mid_send, "mid_send", dms);
+    if (s)
+        return s;
+    if (mid->vdtype != (mixed ? PM_F32 : PM_F64))
+        return arg_error("mid.vdtype must match the field");
+    if (mid->nsub != in->nsub)
+        return arg_error("mid.nsub must equal in.nsub");
+    if (mid->x[0] == in->x[0] || mid->x[0] == out->x[0])
+        return arg_error("mid must differ from in and out");
+    const pm::Shape sh = ctx->shape_auto ? pm::Shape{256, 2} : ctx->shape;
+    if (!pm::stage_shape_supported(sh))
+        return arg_error("launch shape wg=%d items=%d is not built for per-stage migration",
+                         sh.wg, sh.items);
+    ctx->last_shape = sh;
+    hipStream_t st = (hipStream_t)stream;
+    const bool timed = ctx->tmax > 0 && ctx->tcount + 1 < ctx->tmax;
+    pm::KArgs k1 = k;  // stage 1: in -> mid, leavers through mid_send
+    k1.out = dmid;
+    k1.send = dms;
+    s = queue_stage(ctx, k1, mixed, 1, sh, st, timed);
+    if (s)
+        return s;
+    pm::KArgs k2 = k;  // stage 2: mid -> out, leavers through send
+    k2.in = dmid;
+    return queue_stage(ctx, k2, mixed, 2, sh, st, timed);
 }
 
 pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,

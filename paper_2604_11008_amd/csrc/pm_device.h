@@ -30,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pm_internal.h"
 
 namespace pm {
@@ -1179,7 +1181,12 @@ __global__ __launch_bounds__(WG) void k_classify(const KArgs a)
 // With APPEND the job is indexed by destination t and also appends to
 // out[t] after its stayers (the fused step); the (t, stay) job writes
 // out.count[t].
-template <typename FT, bool APPEND>
+template <typename FT>
+__device__ __forceinline__ void put_record_x(const DPool &P, int64_t at, const double X[3],
+                                             const FT V[3], const double Xs[3], const FT Vs[3],
+                                             const FT A[3], FT tau, uint64_t id);
+
+template <typename FT, bool APPEND, bool EXT>
 __global__ __launch_bounds__(256) void k_route(const KArgs a)
 {
     __shared__ uint32_t wcnt[4];
@@ -1294,9 +1301,24 @@ __global__ __launch_bounds__(256) void k_route(const KArgs a)
                     }
                     const FT t = ((const FT *)a.ws.stg_tau)[from];
                     const uint64_t idv = a.ws.stg_id[from];
-                    put_record<FT>(a.send, sbase + slot, X, V, t, idv);
-                    if (APPEND && off + slot < ocap)
-                        put_record<FT>(a.out, obase + off + slot, X, V, t, idv);
+                    if constexpr (EXT) {
+                        double Xs[3];
+                        FT Vs[3], A[3];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            Xs[c] = a.ws.stg_xs[c][from];
+                            Vs[c] = ((const FT *)a.ws.stg_vs[c])[from];
+                            A[c] = ((const FT *)a.ws.stg_a[c])[from];
+                        }
+                        put_record_x<FT>(a.send, sbase + slot, X, V, Xs, Vs, A, t, idv);
+                        if (APPEND && off + slot < ocap)
+                            put_record_x<FT>(a.out, obase + off + slot, X, V, Xs, Vs, A, t,
+                                             idv);
+                    } else {
+                        put_record<FT>(a.send, sbase + slot, X, V, t, idv);
+                        if (APPEND && off + slot < ocap)
+                            put_record<FT>(a.out, obase + off + slot, X, V, t, idv);
+                    }
                 }
             }
             run += tot;
@@ -1516,10 +1538,306 @@ __global__ __launch_bounds__(256) void k_fill(uint64_t *p, int64_t words)
 }
 
 // ---------------------------------------------------------------------------
+// migration after each RK2 stage (the paper's scheme, Sect. 3.2.2): the
+// mid-step record carries X_n, V_n, X*, V* and the stage-1 acceleration a
+// ---------------------------------------------------------------------------
+
+// Stage 1 of the Heun step: X* = X + dt V, V* = V + dt a, a = f (U(X) - V)/tau + g
+// (the same operations as advance_one's first stage).
+template <typename FT, bool HALO, bool NL>
+__device__ __forceinline__ void heun_stage1(const KArgs &a, const double X[3], const FT V[3],
+                                            FT tau, double Xs[3], FT Vs[3], FT A1[3],
+                                            uint32_t &fl)
+{
+    FT U1[3], s1[3];
+    interp<FT, HALO>(a.f, X, U1, fl);
+    const FT it = (FT)1 / tau;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        s1[c] = U1[c] - V[c];
+    if (NL) {
+        const FT f1 = drag_factor<FT>(kkappa<FT>(a), tau, s1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            s1[c] = f1 * s1[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        A1[c] = fma(s1[c], it, kg<FT>(a, c));
+        Vs[c] = fma(kdt<FT>(a), A1[c], V[c]);
+        Xs[c] = fma(a.dt, (double)V[c], X[c]);
+    }
+}
+
+// Stage 2 in the new owner: X' = X + dt/2 (V + V*), V' = V + dt/2 (a + a(X*, V*)).
+template <typename FT, bool HALO, bool NL>
+__device__ __forceinline__ void heun_stage2(const KArgs &a, double X[3], FT V[3],
+                                            const double Xs[3], const FT Vs[3],
+                                            const FT A1[3], FT tau, uint32_t &fl)
+{
+    FT U2[3], s2[3];
+    interp<FT, HALO>(a.f, Xs, U2, fl);
+    const FT it = (FT)1 / tau;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        s2[c] = U2[c] - Vs[c];
+    if (NL) {
+        const FT f2 = drag_factor<FT>(kkappa<FT>(a), tau, s2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            s2[c] = f2 * s2[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const FT A2 = fma(s2[c], it, kg<FT>(a, c));
+        X[c] = fma(a.half_dt, (double)V[c] + (double)Vs[c], X[c]);
+        V[c] = fma(khdt<FT>(a), A1[c] + A2, V[c]);
+    }
+}
+
+// X_n of a stage-1 leaver in the receiver's periodic image: the same +-L as
+// X* (x - L leaving through L, x + L leaving through 0), plain arithmetic.
+__device__ __forceinline__ double shifted_plain(const DDecomp &dc, int a, int k, int o, double x)
+{
+    if (o > 0 && k == dc.p[a] - 1)
+        return x - dc.L[a];
+    if (o < 0 && k == 0)
+        return x + dc.L[a];
+    return x;
+}
+
+template <typename FT>
+__device__ __forceinline__ void put_record_x(const DPool &P, int64_t at, const double X[3],
+                                             const FT V[3], const double Xs[3], const FT Vs[3],
+                                             const FT A[3], FT tau, uint64_t id)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        __builtin_nontemporal_store(X[c], &P.x[c][at]);
+        __builtin_nontemporal_store(V[c], &((FT *)P.v[c])[at]);
+        __builtin_nontemporal_store(Xs[c], &P.xs[c][at]);
+        __builtin_nontemporal_store(Vs[c], &((FT *)P.vs[c])[at]);
+        __builtin_nontemporal_store(A[c], &((FT *)P.a[c])[at]);
+    }
+    __builtin_nontemporal_store(tau, &((FT *)P.tau)[at]);
+    __builtin_nontemporal_store(id, &P.id[at]);
+}
+
+template <typename FT>
+__device__ __forceinline__ void put_staged_x(const DWS &ws, int64_t at, const double X[3],
+                                             const FT V[3], const double Xs[3], const FT Vs[3],
+                                             const FT A[3], FT tau, uint64_t id, int d)
+{
+    put_staged<FT>(ws, at, X, V, tau, id, d);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        ws.stg_xs[c][at] = Xs[c];
+        ((FT *)ws.stg_vs[c])[at] = Vs[c];
+        ((FT *)ws.stg_a[c])[at] = A[c];
+    }
+}
+
+// The stash of a stage-1 tile: mid-step records.
+template <int WG, int ITEMS, typename FT>
+struct TileStashX {
+    static constexpr int T = WG * ITEMS;
+    double x[3][T], xs[3][T];
+    FT v[3][T], vs[3][T], a[3][T];
+    FT tau[T];
+    uint64_t id[T];
+    uint32_t code[T];
+};
+
+template <int WG, int ITEMS, typename FT>
+__device__ __forceinline__ void scatter_stash_x(const KArgs &a, const TileLds<WG, ITEMS> &L,
+                                                const TileStashX<WG, ITEMS, FT> &S,
+                                                uint32_t &fl)
+{
+    const int tid = threadIdx.x;
+    const int s = L.h.s;
+    const int64_t obase = a.out.base[s], ocap = a.out.cap[s];
+    const int64_t g0 = a.ws.stg_start[L.h.sl];
+    const int64_t gcap = a.ws.stg_start[L.h.sl + 1] - g0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int i = k * WG + tid;
+        const uint32_t code = S.code[i];
+        const int b = (int)(code & 0xffu);
+        if (b == 0xff)
+            continue;
+        double X[3], Xs[3];
+        FT V[3], Vs[3], A[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            X[c] = S.x[c][i];
+            Xs[c] = S.xs[c][i];
+            V[c] = S.v[c][i];
+            Vs[c] = S.vs[c][i];
+            A[c] = S.a[c][i];
+        }
+        if (b == PM_STAY) {
+            const int64_t slot = (int64_t)L.base[0] + (code >> 8);
+            if (slot < ocap)
+                put_record_x<FT>(a.out, obase + slot, X, V, Xs, Vs, A, S.tau[i], S.id[i]);
+            else
+                fl |= PM_F_DEST_OVERFLOW;
+        } else {
+            const int64_t m = (int64_t)L.base[1] + (code >> 8);
+            if (m < gcap)
+                put_staged_x<FT>(a.ws, g0 + m, X, V, Xs, Vs, A, S.tau[i], S.id[i], b);
+            else
+                fl |= PM_F_SEND_OVERFLOW;
+        }
+    }
+    publish_counts<WG, ITEMS>(a, L);
+}
+
+// The fused kernel of one stage of per-stage migration, with the tile
+// pipeline of k_step.  STAGE 1: plain records of `in` -> stage 1 ->
+// classified by X* -> mid-step records to `out` / the staging area.
+// STAGE 2: mid-step records of `in` -> stage 2 -> classified by X' -> plain
+// records to `out` / the staging area.
+template <int WG, int ITEMS, typename FT, bool HALO, bool NL, int STAGE>
+__global__ __launch_bounds__(WG) void k_stage(const KArgs a)
+{
+    constexpr int NW = WG / 64;
+    __shared__ TileLds<WG, ITEMS> L[2];
+    using Stash = typename std::conditional<STAGE == 1, TileStashX<WG, ITEMS, FT>,
+                                            TileStash<WG, ITEMS, FT>>::type;
+    __shared__ Stash S;
+    uint32_t *hdr = a.ws.hdr;
+    if (flags_now(hdr) & PM_F_LAYOUT)
+        return;
+    const int64_t total = hdr[kHdrTiles];
+    const int tid = threadIdx.x, w = tid >> 6;
+    uint32_t fl = 0;
+    int cur = 0;
+    bool pend = false;
+
+    while (next_tile<WG, ITEMS>(a, L[cur], total)) {
+        TileLds<WG, ITEMS> &C = L[cur];
+        const int s = C.h.s;
+        const int64_t first = C.h.first;
+        const int nitems = C.h.nitems;
+        int own[3];
+        owner_xyz(a.dc, s, own);
+
+        double X[ITEMS][3], Xs[ITEMS][3];
+        FT V[ITEMS][3], Vs[ITEMS][3], A[ITEMS][3], tau[ITEMS];
+        uint64_t id[ITEMS];
+        int d[ITEMS];
+        uint32_t rank[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int i = k * WG + tid;
+            const int64_t p = first + (i < nitems ? i : nitems - 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                X[k][c] = __builtin_nontemporal_load(&a.in.x[c][p]);
+                V[k][c] = __builtin_nontemporal_load(&((const FT *)a.in.v[c])[p]);
+                if (STAGE == 2) {
+                    Xs[k][c] = __builtin_nontemporal_load(&a.in.xs[c][p]);
+                    Vs[k][c] = __builtin_nontemporal_load(&((const FT *)a.in.vs[c])[p]);
+                    A[k][c] = __builtin_nontemporal_load(&((const FT *)a.in.a[c])[p]);
+                }
+            }
+            tau[k] = __builtin_nontemporal_load(&((const FT *)a.in.tau)[p]);
+            id[k] = __builtin_nontemporal_load(&a.in.id[p]);
+        }
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            d[k] = 0xff;
+            if (k * WG + tid < nitems) {
+                if (STAGE == 1) {
+                    heun_stage1<FT, HALO, NL>(a, X[k], V[k], tau[k], Xs[k], Vs[k], A[k], fl);
+                    d[k] = classify(a.dc, own, Xs[k], fl);
+                } else {
+                    heun_stage2<FT, HALO, NL>(a, X[k], V[k], Xs[k], Vs[k], A[k], tau[k], fl);
+                    d[k] = classify(a.dc, own, X[k], fl);
+                }
+            }
+        }
+
+        tile_ranks<WG, ITEMS>(C, d, rank);
+        publish_aggregate<WG, ITEMS>(a, C);
+
+        if (pend) {
+            TileLds<WG, ITEMS> &P = L[cur ^ 1];
+            walk_back<WG, ITEMS>(a, P);
+            __syncthreads();
+            if constexpr (STAGE == 1)
+                scatter_stash_x<WG, ITEMS, FT>(a, P, S, fl);
+            else
+                scatter_stash<WG, ITEMS, FT>(a, P, S, fl);
+        }
+
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int i = k * WG + tid;
+            uint32_t code = 0xffu;
+            if (d[k] != 0xff) {
+                const int b = d[k];
+                const int e = k * NW + w;
+                code = ((C.cnt[b == PM_STAY ? 0 : 1][e] + rank[k]) << 8) | (uint32_t)b;
+                if (b != PM_STAY) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        if (STAGE == 1) {
+                            Xs[k][c] = shifted(a.dc, c, own[c], dir_o(b, c), Xs[k][c]);
+                            X[k][c] = shifted_plain(a.dc, c, own[c], dir_o(b, c), X[k][c]);
+                        } else {
+                            X[k][c] = shifted(a.dc, c, own[c], dir_o(b, c), X[k][c]);
+                        }
+                    }
+                }
+            }
+            if constexpr (STAGE == 1) {
+                S.code[i] = code;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    S.x[c][i] = X[k][c];
+                    S.v[c][i] = V[k][c];
+                    S.xs[c][i] = Xs[k][c];
+                    S.vs[c][i] = Vs[k][c];
+                    S.a[c][i] = A[k][c];
+                }
+                S.tau[i] = tau[k];
+                S.id[i] = id[k];
+            } else {
+                S.code[i] = code;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    S.x[c][i] = X[k][c];
+                    S.v[c][i] = V[k][c];
+                }
+                S.tau[i] = tau[k];
+                S.id[i] = id[k];
+            }
+        }
+        pend = true;
+        cur ^= 1;
+        __syncthreads();
+    }
+    if (pend) {
+        TileLds<WG, ITEMS> &P = L[cur ^ 1];
+        walk_back<WG, ITEMS>(a, P);
+        __syncthreads();
+        if constexpr (STAGE == 1)
+            scatter_stash_x<WG, ITEMS, FT>(a, P, S, fl);
+        else
+            scatter_stash<WG, ITEMS, FT>(a, P, S, fl);
+    }
+    if (fl)
+        flag_or(hdr, fl);
+}
+
+// ---------------------------------------------------------------------------
 // dispatch over launch shapes and precisions
 // ---------------------------------------------------------------------------
 
 #define PM_SHAPES(X) X(256, 1) X(256, 2) X(256, 4) X(256, 8) X(512, 1) X(512, 2) X(512, 4)
+// per-stage migration: tiles of at most 1024 mid-step records fit the LDS
+#define PM_STAGE_SHAPES(X) X(256, 1) X(256, 2) X(256, 4) X(512, 1) X(512, 2)
 
 // The fused and advance kernels come in element type x halo x drag law
 // variants; Kern<W, I>::step/advance pick the one for the launch.
@@ -1563,6 +1881,37 @@ struct Kern {
                        : advance_t<FT, true, false, SG>(a, grid, st))
                  : (nl ? advance_t<FT, false, true, SG>(a, grid, st)
                        : advance_t<FT, false, false, SG>(a, grid, st));
+    }
+    template <typename FT, bool H, bool NL, int STG>
+    static hipError_t stage_t(const KArgs &a, int grid, hipStream_t st)
+    {
+        hipLaunchKernelGGL((k_stage<W, I, FT, H, NL, STG>), dim3(grid), dim3(W), 0, st, a);
+        return hipGetLastError();
+    }
+    template <typename FT, bool H, bool NL, int STG>
+    static int stage_occ_t()
+    {
+        int nb = 1;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_stage<W, I, FT, H, NL, STG>),
+                                                           W, 0);
+        return nb;
+    }
+    // the halo x drag-law variants of one stage of per-stage migration
+    template <typename FT, int STG>
+    static hipError_t stage_ft(const KArgs &a, int grid, hipStream_t st)
+    {
+        const bool h = a.f.halo != 0, nl = a.drag != 0;
+        return h ? (nl ? stage_t<FT, true, true, STG>(a, grid, st)
+                       : stage_t<FT, true, false, STG>(a, grid, st))
+                 : (nl ? stage_t<FT, false, true, STG>(a, grid, st)
+                       : stage_t<FT, false, false, STG>(a, grid, st));
+    }
+    template <typename FT, int STG>
+    static int stage_occ_ft(bool h, bool nl)
+    {
+        return h ? (nl ? stage_occ_t<FT, true, true, STG>() : stage_occ_t<FT, true, false, STG>())
+                 : (nl ? stage_occ_t<FT, false, true, STG>()
+                       : stage_occ_t<FT, false, false, STG>());
     }
     template <typename FT, bool SG>
     static int occupancy_ft(bool h, bool nl)

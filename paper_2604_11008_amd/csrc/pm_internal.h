@@ -49,6 +49,11 @@ struct DPool {
     void *v[3];
     void *tau;
     uint64_t *id;
+    // mid-step records of per-stage migration only (else null): the stage-1
+    // position and velocity and the stage-1 acceleration
+    double *xs[3];
+    void *vs[3];
+    void *a[3];
 };
 
 struct DWS {
@@ -64,6 +69,9 @@ struct DWS {
     double *stg_v[3];      // read as float in the mixed mode
     double *stg_tau;
     uint64_t *stg_id;
+    double *stg_xs[3];     // per-stage migration's extra fields
+    double *stg_vs[3];
+    double *stg_a[3];
     uint8_t *stg_d;
     int64_t max_tiles;
     int64_t pool_extent;
@@ -109,7 +117,8 @@ hipError_t launch_advance(const KArgs &a, Shape sh, bool mixed, int grid, hipStr
 hipError_t launch_classify(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);
 hipError_t launch_compact(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);
 hipError_t launch_append(const KArgs &a, bool mixed, int grid, hipStream_t st);
-hipError_t launch_route(const KArgs &a, bool mixed, bool append, hipStream_t st);
+hipError_t launch_route(const KArgs &a, bool mixed, bool append, hipStream_t st,
+                        bool ext = false);
 hipError_t launch_interp(const KArgs &a, bool mixed, int64_t n, const double *x,
                          const double *y, const double *z, void *ux, void *uy,
                          void *uz, hipStream_t st);
@@ -134,6 +143,16 @@ hipError_t launch_advance_mac_f64(const KArgs &a, Shape sh, int grid, hipStream_
 hipError_t launch_advance_mac_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
 int step_occupancy_mac_f64(Shape sh, bool halo, bool nonlinear);
 int step_occupancy_mac_f32(Shape sh, bool halo, bool nonlinear);
+// per-stage migration: the fused kernel of stage 1 or 2 (pm_staged_f64.hip,
+// pm_staged_f32.hip)
+bool stage_shape_supported(Shape sh);
+hipError_t launch_stage(const KArgs &a, Shape sh, bool mixed, int stage, int grid,
+                        hipStream_t st);
+int stage_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, int stage);
+hipError_t launch_stage_f64(const KArgs &a, Shape sh, int stage, int grid, hipStream_t st);
+hipError_t launch_stage_f32(const KArgs &a, Shape sh, int stage, int grid, hipStream_t st);
+int stage_occupancy_f64(Shape sh, bool halo, bool nonlinear, int stage);
+int stage_occupancy_f32(Shape sh, bool halo, bool nonlinear, int stage);
 bool shape_supported(Shape sh);
 
 }  // namespace pm

@@ -4,6 +4,14 @@
 #include "pm_device.h"
 
 namespace pm {
+bool stage_shape_supported(Shape sh)
+{
+#define PM_ONE(W, I) if (sh.wg == W && sh.items == I) return true;
+    PM_STAGE_SHAPES(PM_ONE)
+#undef PM_ONE
+    return false;
+}
+
 bool shape_supported(Shape sh)
 {
 #define PM_ONE(W, I) if (sh.wg == W && sh.items == I) return true;
@@ -66,20 +74,27 @@ hipError_t launch_append(const KArgs &a, bool mixed, int grid, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_route(const KArgs &a, bool mixed, bool append, hipStream_t st)
+hipError_t launch_route(const KArgs &a, bool mixed, bool append, hipStream_t st, bool ext)
 {
     const int64_t jobs = (int64_t)a.sub_count * 27;
     const int grid = (int)(jobs < 4096 ? jobs : 4096);
+    if (ext) {  // mid-step records of per-stage migration (always appended)
+        if (mixed)
+            hipLaunchKernelGGL((k_route<float, true, true>), dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_route<double, true, true>), dim3(grid), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
     if (mixed) {
         if (append)
-            hipLaunchKernelGGL((k_route<float, true>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_route<float, true, false>), dim3(grid), dim3(256), 0, st, a);
         else
-            hipLaunchKernelGGL((k_route<float, false>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_route<float, false, false>), dim3(grid), dim3(256), 0, st, a);
     } else {
         if (append)
-            hipLaunchKernelGGL((k_route<double, true>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_route<double, true, false>), dim3(grid), dim3(256), 0, st, a);
         else
-            hipLaunchKernelGGL((k_route<double, false>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_route<double, false, false>), dim3(grid), dim3(256), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -154,6 +169,20 @@ hipError_t launch_step(const KArgs &a, Shape sh, bool mixed, int grid, hipStream
 hipError_t launch_advance(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st)
 {
     return mixed ? launch_advance_f32(a, sh, grid, st) : launch_advance_f64(a, sh, grid, st);
+}
+
+hipError_t launch_stage(const KArgs &a, Shape sh, bool mixed, int stage, int grid,
+                        hipStream_t st)
+{
+    return mixed ? launch_stage_f32(a, sh, stage, grid, st)
+                 : launch_stage_f64(a, sh, stage, grid, st);
+}
+
+int stage_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, int stage)
+{
+    const int nb = mixed ? stage_occupancy_f32(sh, halo, nonlinear, stage)
+                         : stage_occupancy_f64(sh, halo, nonlinear, stage);
+    return nb < 1 ? 1 : nb;
 }
 
 int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, bool stagger)

@@ -51,6 +51,20 @@ class _Send(C.Structure):
                 ("id", C.c_void_p)]
 
 
+class _StageParticles(C.Structure):
+    _fields_ = [("nsub", C.c_int32), ("vdtype", C.c_int32), ("base", C.c_void_p),
+                ("cap", C.c_void_p), ("count", C.c_void_p), ("x", C.c_void_p * 3),
+                ("v", C.c_void_p * 3), ("xs", C.c_void_p * 3), ("vs", C.c_void_p * 3),
+                ("a", C.c_void_p * 3), ("tau", C.c_void_p), ("id", C.c_void_p)]
+
+
+class _StageSend(C.Structure):
+    _fields_ = [("base", C.c_void_p), ("cap", C.c_void_p), ("count", C.c_void_p),
+                ("x", C.c_void_p * 3), ("v", C.c_void_p * 3), ("xs", C.c_void_p * 3),
+                ("vs", C.c_void_p * 3), ("a", C.c_void_p * 3), ("tau", C.c_void_p),
+                ("id", C.c_void_p)]
+
+
 class _Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("g", C.c_double * 3), ("drag", C.c_int32),
                 ("pad_", C.c_int32), ("nu", C.c_double), ("density_ratio", C.c_double)]
@@ -85,6 +99,7 @@ def lib():
             "pm_classify_scan_pack": ([vp, vp, vp, vp, i32, i32, vp], C.c_int),
             "pm_compact_append": ([vp, vp, vp, vp, vp, i32, i32, vp], C.c_int),
             "pm_step": ([vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+            "pm_step_staged": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "pm_get_status": ([vp, vp, vp], C.c_int),
             "pm_set_tuning": ([vp, vp], C.c_int),
             "pm_get_tuning": ([vp, vp], C.c_int),
@@ -250,6 +265,45 @@ class DevicePool:
         return int((self.base + self.cap).max().item()) if self.nseg else 0
 
 
+class DeviceStagePool(DevicePool):
+    """Mid-step records of per-stage migration on the device: the pool's
+    arrays plus xs (X*, float64), vs (V*) and a (dV/dt), like v."""
+
+    def __init__(self, x, v, xs, vs, a, tau, ids, base, cap, count):
+        super().__init__(x, v, tau, ids, base, cap, count)
+        self.xs, self.vs, self.a = xs, vs, a
+        if xs.shape != x.shape or xs.dtype != torch.float64:
+            raise PMError("xs must be a float64 (3, size) tensor")
+        for t in (vs, a):
+            if t.shape != v.shape or t.dtype != v.dtype or not t.is_contiguous():
+                raise PMError("vs and a must match v")
+
+    @classmethod
+    def empty(cls, base, cap, vdtype=torch.float64, device="cuda", size=None):
+        p = DevicePool.empty(base, cap, vdtype=vdtype, device=device, size=size)
+        return cls(p.x, p.v, torch.zeros_like(p.x), torch.zeros_like(p.v),
+                   torch.zeros_like(p.v), p.tau, p.id, p.base, p.cap, p.count)
+
+    def to_host(self):
+        h = super().to_host()
+        h.xs, h.vs, h.a = self.xs.cpu().numpy(), self.vs.cpu().numpy(), self.a.cpu().numpy()
+        return h
+
+    def _arr(self, t):
+        return (C.c_void_p * 3)(*[_p(t[k]) for k in range(3)])
+
+    def stage_particles(self):
+        return _StageParticles(self.nseg, self.vdtype, _p(self.base), _p(self.cap),
+                               _p(self.count), self._arr(self.x), self._arr(self.v),
+                               self._arr(self.xs), self._arr(self.vs), self._arr(self.a),
+                               _p(self.tau), _p(self.id))
+
+    def stage_sendbufs(self):
+        return _StageSend(_p(self.base), _p(self.cap), _p(self.count), self._arr(self.x),
+                          self._arr(self.v), self._arr(self.xs), self._arr(self.vs),
+                          self._arr(self.a), _p(self.tau), _p(self.id))
+
+
 @dataclass
 class Params:
     """pm_params: time step, gravity, drag law ("stokes" or "nonlinear") and,
@@ -353,6 +407,19 @@ class Context:
         sc = self._send(send, pin.nseg)
         _check(lib().pm_step(self.h, C.byref(field.c), C.byref(decomp.c), C.byref(pc),
                              C.byref(oc), C.byref(sc), C.byref(params.c), _stream(stream)))
+
+    def step_staged(self, field, decomp, pin, mid, mid_send, pout, send, params, stream=None):
+        """Migration after each RK2 stage: pin -> mid (DeviceStagePool, leavers
+        through mid_send) -> pout (leavers through send)."""
+        pc = self._pool(pin, "in")
+        oc = self._pool(pout, "out")
+        sc = self._send(send, pin.nseg)
+        self._pool(mid, "mid")
+        self._send(mid_send, pin.nseg)
+        mc, msc = mid.stage_particles(), mid_send.stage_sendbufs()
+        _check(lib().pm_step_staged(self.h, C.byref(field.c), C.byref(decomp.c), C.byref(pc),
+                                    C.byref(mc), C.byref(msc), C.byref(oc), C.byref(sc),
+                                    C.byref(params.c), _stream(stream)))
 
     def get_status(self, stream=None):
         f = C.c_uint32(0)

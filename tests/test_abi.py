@@ -40,6 +40,9 @@ def header_layout(tmp_path):
         "pm_sendbufs": ["base", "cap", "count", "x", "v", "tau", "id"],
         "pm_params": ["dt", "g", "drag", "nu", "density_ratio"],
         "pm_tuning": ["wg", "items", "blocks_per_cu"],
+        "pm_stage_particles": ["nsub", "vdtype", "base", "cap", "count", "x", "v", "xs", "vs",
+                               "a", "tau", "id"],
+        "pm_stage_sendbufs": ["base", "cap", "count", "x", "v", "xs", "vs", "a", "tau", "id"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pm.h"', 'int main(void) {']
     for st, fields in probes.items():
@@ -64,7 +67,8 @@ def test_binding_struct_layout_matches_header(tmp_path):
     from paper_2604_11008_amd import pm
     probes, ref = header_layout(tmp_path)
     cls = {"pm_field": pm._Field, "pm_decomp": pm._Decomp, "pm_particles": pm._Particles,
-           "pm_sendbufs": pm._Send, "pm_params": pm._Params, "pm_tuning": pm._Tuning}
+           "pm_sendbufs": pm._Send, "pm_params": pm._Params, "pm_tuning": pm._Tuning,
+           "pm_stage_particles": pm._StageParticles, "pm_stage_sendbufs": pm._StageSend}
     for st, fields in probes.items():
         c = cls[st]
         assert ctypes.sizeof(c) == ref[(st, "sizeof")], st
