@@ -40,6 +40,8 @@ WORKLOADS = {
           "8x8x8 subdomains",
     "C5": "1024^3 periodic FP32 field, 2^28 blob-clustered particles (FP64 positions, "
           "FP32 velocity/tau), 8x8x8 subdomains",
+    "CP": "750^3 FP64 field with a one-cell halo, 52,734,375 uniform particles (750^3/8, "
+          "the paper's per-rank share), 1 subdomain, tau log-uniform [0.01,1], g=(0,0,-1)",
 }
 
 
@@ -58,6 +60,12 @@ def parse():
     ap.add_argument("--stagger", action="store_true",
                     help="read the field as MAC-staggered (component c on the faces "
                          "normal to axis c)")
+    ap.add_argument("--staged", action="store_true",
+                    help="migrate after each RK2 stage (the paper's scheme) instead of once "
+                         "per step")
+    ap.add_argument("--migration-only", action="store_true",
+                    help="also time the exchange alone (classify/scan/pack + "
+                         "compact/append, no advance) on the timed state")
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
     ap.add_argument("--tune", default=None, help="wg,items[,blocks_per_cu] or 'auto'")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
@@ -182,6 +190,19 @@ def main():
     # v0 = U(x0), interpolated on the device
     pa.v.copy_(ctx.interp(field, pa.x))
     params = pm.Params(wl.dt, wl.g, drag=args.drag)
+    mid = msend = None
+    if args.staged:
+        if args.graph or args.tune == "auto" or args.stagger:
+            raise SystemExit("--staged runs eager, without the autotuner, on collocated fields")
+        mid = pm.DeviceStagePool.empty(pool.base, pool.cap, vdtype=vdt, device=dev, size=size)
+        msend = pm.DeviceStagePool.empty(sb, sc, vdtype=vdt, device=dev, size=send.size)
+
+    def do_step(src, dst):
+        if args.staged:
+            ctx.step_staged(field, dc, src, mid, msend, dst, send, params)
+        else:
+            ctx.step(field, dc, src, dst, send, params)
+
     if args.tune == "auto":
         ctx.autotune(field, dc, pa, pb, send, params, cache_path=args.tune_cache)
     elif args.tune:
@@ -196,7 +217,7 @@ def main():
 
     # warm-up
     for _ in range(args.warmup):
-        ctx.step(field, dc, pa, pb, send, params)
+        do_step(pa, pb)
         pa, pb = pb, pa
     f = ctx.get_status()
     if f:
@@ -205,11 +226,17 @@ def main():
     # algorithmic bytes of a step of this state (untimed): touched field nodes
     # and migrants
     touched = ctx.touched_nodes(field, pa, params)
-    ctx.step(field, dc, pa, pb, send, params)
+    do_step(pa, pb)
     migrants = int(send.count.sum().item())
     pa, pb = pb, pa
-    alg = accounting.step_algorithmic_bytes(npart, migrants, touched,
-                                            "mixed" if mixed else "f64")
+    if args.staged:
+        migrants1 = int(msend.count.sum().item())
+        alg = accounting.staged_algorithmic_bytes(npart, migrants1, migrants, touched,
+                                                  "mixed" if mixed else "f64")
+        alg["fused_kernel"] = alg["stage_kernels"]
+    else:
+        alg = accounting.step_algorithmic_bytes(npart, migrants, touched,
+                                                "mixed" if mixed else "f64")
 
     # the state the timed steps start from, so the graph replays below start
     # from it too (kernel time drifts as particles disperse from their sorted
@@ -218,11 +245,11 @@ def main():
 
     # timed region
     if not args.graph:
-        ctx.set_timing(args.steps)
+        ctx.set_timing(args.steps * (2 if args.staged else 1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.step(field, dc, pa, pb, send, params)
+        do_step(pa, pb)
         pa, pb = pb, pa
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -231,6 +258,8 @@ def main():
         raise SystemExit(f"flags after timed steps: {pm.flag_names(f)}")
     ms_step = (t1 - t0) * 1e3 / args.steps
     k_total, k_each = (ctx.kernel_times() if not args.graph else (None, []))
+    if args.staged and k_each:  # the two stage kernels of a step, summed
+        k_each = [a + b for a, b in zip(k_each[0::2], k_each[1::2])]
     k_ms = (k_total / len(k_each)) if k_each else None
     print(f"[bench] {args.steps} steps: {ms_step:.4f} ms/step; fused kernel "
           f"{k_ms if k_ms is None else round(k_ms, 4)} ms", file=sys.stderr, flush=True)
@@ -246,18 +275,55 @@ def main():
         tpath = args.traffic or os.path.join(ROOT, "profiles",
                                              f"k_step_{args.config}_traffic.json")
         traffic = None
-        if os.path.exists(tpath) and json.load(open(tpath)).get("kernel") == variant:
+        if os.path.exists(tpath) and json.load(open(tpath)).get("kernel") == variant \
+                and not args.staged:
             traffic = profsum.load_traffic(tpath)
         roof = {"bound": "hbm", "achieved": round(achieved, 1),
                 "peak": accounting.HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / accounting.HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "k_step (fused interpolate/advance/classify/scan/scatter)",
+                "kernel": ("k_stage<1> + k_stage<2> (the two per-stage fused kernels)"
+                           if args.staged else
+                           "k_step (fused interpolate/advance/classify/scan/scatter)"),
                 "kernel_ms": round(k_ms, 5),
                 "kernel_ms_first_last": [round(k_each[0], 5), round(k_each[-1], 5)],
                 "algorithmic_bytes_per_launch": alg["fused_kernel"]}
 
     extra = {}
-    if not args.graph:
+    if args.staged:
+        extra["stage1_migrants_per_step"] = migrants1
+    if args.migration_only:
+        # the exchange alone, one stage's worth (what the paper times as
+        # packing + unpacking), on the timed state advanced by one step in
+        # place on a copy, so that its leavers are still in their old owners
+        ctx.set_timing(0)
+        sendm = pm.DevicePool.empty(sb, sc, vdtype=vdt, device=dev)
+        outm = pm.DevicePool.empty(pool.base, pool.cap, vdtype=vdt, device=dev, size=size)
+        work = pm.DevicePool(pa.x.clone(), pa.v.clone(), pa.tau.clone(), pa.id.clone(),
+                             pa.base, pa.cap, pa.count.clone())
+        ctx.interp_advance(field, work, params)
+        for _ in range(2):
+            ctx.classify_scan_pack(dc, work, sendm)
+            ctx.compact_append(dc, work, sendm, outm)
+        torch.cuda.synchronize()
+        reps = 10
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            ctx.classify_scan_pack(dc, work, sendm)
+        e[1].record()
+        for _ in range(reps):
+            ctx.compact_append(dc, work, sendm, outm)
+        e[2].record()
+        torch.cuda.synchronize()
+        f = ctx.get_status()
+        if f:
+            raise SystemExit(f"flags after the exchange timing: {pm.flag_names(f)}")
+        extra["migration_only_ms"] = {
+            "classify_scan_pack": round(e[0].elapsed_time(e[1]) / reps, 4),
+            "compact_append": round(e[1].elapsed_time(e[2]) / reps, 4),
+            "migrants": int(sendm.count.sum().item())}
+        del sendm, outm, work
+    if not args.graph and not args.staged:
         # the same steps replayed from captured HIP graphs (two graphs: A->B, B->A)
         ctx.set_timing(0)
         ctx.set_graph(True)
@@ -359,6 +425,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "mixed-f32/f64" if mixed else "f64", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}" +
+                   (", migration after each RK2 stage" if args.staged else "") +
                    (f" (run at {args.precision})" if args.precision != "auto" else "") +
                    (", nonlinear drag" if args.drag == "nonlinear" else "") +
                    (", MAC-staggered field" if args.stagger else ""),

@@ -35,6 +35,27 @@ def step_algorithmic_bytes(n_particles, migrants, touched_nodes, mode):
             "per_particle_record": s_rec, "per_node": 3 * s_f}
 
 
+def mid_record_bytes(mode):
+    """Mid-step record of per-stage migration: X_n, X* (float64) and V_n, V*,
+    dV/dt, tau (float64, or float32 in the mixed mode), id."""
+    s = 8 if mode == "f64" else 4
+    return 6 * 8 + 10 * s + 8
+
+
+def staged_algorithmic_bytes(n_particles, migrants1, migrants2, touched_nodes, mode):
+    """Both stage kernels of per-stage migration: stage 1 reads each plain
+    record and writes a mid-step record, stage 2 reads it back and writes a
+    plain record; every touched field node is read at least once (the union
+    over both stages, a lower bound); leavers of each stage go to and come
+    back from their send buffers."""
+    s_rec, s_mid = record_bytes(mode), mid_record_bytes(mode)
+    s_f = field_value_bytes(mode)
+    kernels = n_particles * 2 * (s_rec + s_mid) + touched_nodes * 3 * s_f
+    exchange = migrants1 * 2 * s_mid + migrants2 * 2 * s_rec
+    return {"step": kernels + exchange, "stage_kernels": kernels,
+            "exchange": exchange}
+
+
 def cpu_delegated_model(arrays, bytes_per_value, particles, link_gbps, core_gbps):
     """Sect. 3.2.2: the full particle arrays go device->host over the link,
     are packed and unpacked sequentially at one core's memory bandwidth, and

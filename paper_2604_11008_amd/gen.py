@@ -46,6 +46,13 @@ CONFIGS = {
     "C2S": dict(index=5, n=256, halo=0, k0=8, kmax=32, np=4194304, dist="uniform",
                 tau=("loguniform", 0.01, 1.0), g=(0.0, 0.0, -1.0), dt="rms",
                 p=(8, 8, 8), steps=20, mode="f64"),
+    # the paper's per-rank share of its particle-communication measurement
+    # (Sect. 3.2.2: a 1500^3 grid and 750^3 particles over 8 GPUs): a 750^3
+    # field with a one-cell halo and 750^3 / 8 uniform particles in one
+    # subdomain (26 periodic self-neighbours)
+    "CP": dict(index=6, n=750, halo=1, k0=16, kmax=64, np=52734375, dist="uniform",
+               tau=("loguniform", 0.01, 1.0), g=(0.0, 0.0, -1.0), dt="rule",
+               p=(1, 1, 1), steps=20, mode="f64"),
 }
 
 

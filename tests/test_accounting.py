@@ -36,3 +36,12 @@ def test_record_sizes():
     assert accounting.record_bytes("mixed") == 48
     b = accounting.step_algorithmic_bytes(1000, 10, 500, "f64")
     assert b["step"] == 1000 * 128 + 500 * 24 + 10 * 128
+
+
+def test_mid_step_record_is_the_papers_17_arrays():
+    # Sect. 3.2.2: positions and velocities of both RK2 stages, dV/dt, id and
+    # diameter: (2 + 2 + 1) x 3 + 2 = 17 Float64 values per particle
+    assert accounting.mid_record_bytes("f64") == 17 * 8
+    b = accounting.staged_algorithmic_bytes(10, 2, 1, 5, "f64")
+    assert b["stage_kernels"] == 10 * 2 * (64 + 136) + 5 * 24
+    assert b["exchange"] == 2 * 2 * 136 + 1 * 2 * 64
