@@ -321,7 +321,9 @@ pm_status pm_kernel_times(pm_ctx *ctx, int32_t *n, double *total_ms, float *ms,
  * `send`).  Each exchange is the same scan, pack, compact and append as
  * pm_step's.  Collocated fields only; `in` is unchanged; mid must fit the
  * context's pool extent and mid_send its send extent.  Launch shapes with
- * at most 1024 records per tile (default 256 x 2). */
+ * at most 1024 records per tile (default 256 x 2).  Always launched eagerly
+ * (pm_set_graph applies to pm_step); pm_set_timing records both stages'
+ * fused kernels. */
 pm_status pm_step_staged(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
                          const pm_particles *in, pm_stage_particles *mid,
                          pm_stage_sendbufs *mid_send, pm_particles *out,
