@@ -286,6 +286,9 @@ def main():
                            "k_step (fused interpolate/advance/classify/scan/scatter)"),
                 "kernel_ms": round(k_ms, 5),
                 "kernel_ms_first_last": [round(k_each[0], 5), round(k_each[-1], 5)],
+                "kernel_ms_min_median_max": [round(float(np.min(k_each)), 5),
+                                             round(float(np.median(k_each)), 5),
+                                             round(float(np.max(k_each)), 5)],
                 "algorithmic_bytes_per_launch": alg["fused_kernel"]}
 
     extra = {}

@@ -1186,6 +1186,20 @@ __device__ __forceinline__ void put_record_x(const DPool &P, int64_t at, const d
                                              const FT V[3], const double Xs[3], const FT Vs[3],
                                              const FT A[3], FT tau, uint64_t id);
 
+// Particles that subdomain x receives in the directions below d (all 26 for
+// d = 27): the send counts of its neighbours, one per lane of wave 0 (every
+// lane of the wave must call).
+__device__ __forceinline__ int64_t received_before(const KArgs &a, int x, int d)
+{
+    const int dd = threadIdx.x;
+    int64_t c = 0;
+    if (dd < d && dd < 27 && dd != PM_STAY) {
+        c = a.send.count[(int64_t)neighbour(a.dc, x, dd, -1) * 27 + dd];
+        c = c > 0 ? c : 0;
+    }
+    return (int64_t)wave_sum64((uint64_t)c);
+}
+
 template <typename FT, bool APPEND, bool EXT>
 __global__ __launch_bounds__(256) void k_route(const KArgs a)
 {
@@ -1202,17 +1216,15 @@ __global__ __launch_bounds__(256) void k_route(const KArgs a)
         const int x = a.sub_first + (int)(job / 27);
         const int d = (int)(job % 27);
         if (d == PM_STAY) {
-            if (APPEND && tid == 0) {
-                int64_t tot = a.ws.stay[x];
-                for (int dd = 0; dd < 27; ++dd) {
-                    if (dd == PM_STAY)
-                        continue;
-                    const int64_t n = a.send.count[(int64_t)neighbour(a.dc, x, dd, -1) * 27 + dd];
-                    tot += n > 0 ? n : 0;
+            // out.count[x]: the stayers plus everything received, the 26
+            // counts read by 26 lanes at once
+            if (APPEND && tid < 64) {
+                const int64_t tot = a.ws.stay[x] + received_before(a, x, 27);
+                if (tid == 0) {
+                    a.out.count[x] = tot;
+                    if (tot > a.out.cap[x])
+                        fl |= PM_F_DEST_OVERFLOW;
                 }
-                a.out.count[x] = tot;
-                if (tot > a.out.cap[x])
-                    fl |= PM_F_DEST_OVERFLOW;
             }
             continue;
         }
@@ -1231,15 +1243,10 @@ __global__ __launch_bounds__(256) void k_route(const KArgs a)
             gn = a.ws.migtot[src];
         int64_t obase = 0, ocap = 0;
         if (APPEND) {
-            if (tid == 0) {
-                int64_t off = a.ws.stay[x];
-                for (int dd = 0; dd < d; ++dd) {
-                    if (dd == PM_STAY)
-                        continue;
-                    const int64_t c = a.send.count[(int64_t)neighbour(a.dc, x, dd, -1) * 27 + dd];
-                    off += c > 0 ? c : 0;
-                }
-                s_off = off;
+            if (tid < 64) {
+                const int64_t off = a.ws.stay[x] + received_before(a, x, d);
+                if (tid == 0)
+                    s_off = off;
             }
             obase = a.out.base[x];
             ocap = a.out.cap[x];
