@@ -767,30 +767,38 @@ __global__ __launch_bounds__(256) void k_prep(const KArgs a, int mode)
     uint32_t bad = 0;
 
     if ((mode & (kPrepTiles | kPrepStaging)) && blockIdx.x == 0) {
+        __shared__ int64_t segv[PM_MAX_NSUB];
         for (int pass = 0; pass < 2; ++pass) {
             if (!(mode & (pass == 0 ? kPrepTiles : kPrepStaging)))
                 continue;
+            // per-segment values, segments strided over the threads so that a
+            // segment's loads go out together, then scanned in contiguous runs
+            for (int i = tid; i < a.sub_count; i += 256) {
+                const int64_t s = a.sub_first + i;
+                int64_t c = 0;
+                if (pass == 0) {
+                    c = a.in.count[s];
+                    c = c > 0 ? (c + a.tile - 1) / a.tile : 0;
+                } else {
+                    int64_t cp[27];
+#pragma unroll
+                    for (int d = 0; d < 27; ++d)
+                        cp[d] = a.send.cap[s * 27 + d];
+#pragma unroll
+                    for (int d = 0; d < 27; ++d)
+                        c += (d != PM_STAY && cp[d] > 0) ? cp[d] : 0;
+                    c = (c + 15) & ~(int64_t)15;  // 16-aligned staging areas
+                }
+                segv[i] = c;
+            }
+            __syncthreads();
             int64_t v[PER];
             int64_t sum = 0;
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int i = tid * PER + k;
-                int64_t c = 0;
-                if (i < a.sub_count) {
-                    const int64_t s = a.sub_first + i;
-                    if (pass == 0) {
-                        c = a.in.count[s];
-                        c = c > 0 ? (c + a.tile - 1) / a.tile : 0;
-                    } else {
-                        for (int d = 0; d < 27; ++d) {
-                            const int64_t cp = a.send.cap[s * 27 + d];
-                            c += (d != PM_STAY && cp > 0) ? cp : 0;
-                        }
-                        c = (c + 15) & ~(int64_t)15;  // 16-aligned staging areas
-                    }
-                }
-                v[k] = c;
-                sum += c;
+                v[k] = i < a.sub_count ? segv[i] : 0;
+                sum += v[k];
             }
             int64_t total;
             int64_t run = block_scan256(sum, wsum, &total);
@@ -816,6 +824,7 @@ __global__ __launch_bounds__(256) void k_prep(const KArgs a, int mode)
                     bad |= PM_F_LAYOUT;
                 }
             }
+            __syncthreads();  // segv is rewritten by the next pass
         }
     }
 
