@@ -67,7 +67,7 @@ def parse():
                     help="also time the exchange alone (classify/scan/pack + "
                          "compact/append, no advance) on the timed state")
     ap.add_argument("--graph", action="store_true", help="replay captured HIP graphs")
-    ap.add_argument("--tune", default=None, help="wg,items[,blocks_per_cu] or 'auto'")
+    ap.add_argument("--tune", default=None, help="wg,items[,blocks_per_cu[,xcd_block]] or 'auto'")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -268,7 +268,7 @@ def main():
     if k_ms:
         achieved = alg["fused_kernel"] / (k_ms * 1e-3) / 1e9
         from paper_2604_11008_amd import profsum
-        wg, items, _ = ctx.get_tuning()
+        wg, items = ctx.get_tuning()[:2]
         tf = lambda b: "true" if b else "false"  # noqa: E731
         variant = (f"k_step<{wg}, {items}, {'float' if mixed else 'double'}, "
                    f"{tf(wl.halo)}, {tf(args.drag == 'nonlinear')}, {tf(args.stagger)}>")

@@ -213,13 +213,18 @@ typedef struct {
  * shape of the last launch.  blocks_per_cu is the persistent grid's
  * workgroups per compute unit: 0 = the runtime's occupancy estimate; an
  * explicit 1..32 may exceed it (surplus workgroups start as others retire;
- * tiles are claimed by ticket, so this cannot deadlock).  No shape changes
- * any result. */
+ * tiles are claimed by ticket, so this cannot deadlock).  xcd_block is the
+ * tile order of the persistent kernels: 0 = one ticket counter for all
+ * workgroups (tiles in order, each on whichever XCD asks next); 1..65536 =
+ * workgroup b takes its tiles from the counter of XCD b mod 8 and the XCDs
+ * take blocks of xcd_block consecutive tiles in turn, so that each XCD's L2
+ * serves neighbouring tiles (fewer field bytes fetched, not faster on the
+ * measured workloads).  No tuning changes any result. */
 typedef struct {
     int32_t wg;
     int32_t items;
     int32_t blocks_per_cu;
-    int32_t pad_;
+    int32_t xcd_block;
 } pm_tuning;
 
 typedef struct pm_ctx pm_ctx;

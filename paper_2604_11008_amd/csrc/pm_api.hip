@@ -97,6 +97,7 @@ struct pm_ctx {
     bool shape_auto = true;         // no pm_set_tuning / pm_autotune yet
     pm::Shape last_shape{256, 4};   // the shape of the last launch
     int blocks_per_cu = 0;
+    int xcd_block = 0;              // pm_tuning.xcd_block
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
     std::vector<GraphEntry> graphs;
@@ -305,13 +306,23 @@ int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed, bool halo, bool nonli
                     bool stagger)
 {
     // An explicit figure may exceed the runtime's occupancy estimate: workgroups
-    // that do not fit start as others retire, and since tiles are claimed by
-    // ticket when a workgroup runs, no running workgroup waits on one that has
-    // not started.
+    // that do not fit start as others retire.  Tiles are claimed by ticket when
+    // a workgroup runs, so a running workgroup only waits on tiles that a
+    // running workgroup holds or that its ticket group will hand to one: each
+    // group has running workgroups, since workgroups start in index order.
     const int per = ctx->blocks_per_cu > 0 ? ctx->blocks_per_cu
                                            : pm::step_occupancy(sh, mixed, halo, nonlinear,
                                                                 stagger);
     return std::max(1, ctx->cus * per);
+}
+
+// Ticket groups of a persistent launch of `grid` workgroups: one counter, or
+// one per XCD handing out blocks of xcd_block tiles.
+void set_groups(const pm_ctx *ctx, pm::KArgs &k, int grid)
+{
+    const bool grouped = ctx->xcd_block > 0 && grid >= pm::kMaxGroups;
+    k.xg = grouped ? pm::kMaxGroups : 1;
+    k.xb = grouped ? ctx->xcd_block : 1;
 }
 
 int append_cpt(int32_t count) { return std::max(1, 2048 / std::max(1, count)); }
@@ -330,8 +341,10 @@ pm_status queue_step(pm_ctx *ctx, pm::KArgs &k, bool mixed, hipStream_t st, bool
            "prep launch");
     if (timed)
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount], st), "event record");
-    PM_HIP(pm::launch_step(k, sh, mixed, persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0), st),
-           "fused step launch");
+    const int grid =
+        persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
+    set_groups(ctx, k, grid);
+    PM_HIP(pm::launch_step(k, sh, mixed, grid, st), "fused step launch");
     if (timed) {
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount + 1], st), "event record");
         ctx->tcount++;
@@ -489,7 +502,9 @@ pm_status pm_interp_advance(pm_ctx *ctx, const pm_field *field, pm_particles *in
     const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
     k.tile = sh.wg * sh.items;
     PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn, st), "prep launch");
-    PM_HIP(pm::launch_advance(k, sh, mixed, persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0), st),
+    const int grid = persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
+    set_groups(ctx, k, grid);
+    PM_HIP(pm::launch_advance(k, sh, mixed, grid, st),
            "advance launch");
     return PM_OK;
 }
@@ -530,7 +545,9 @@ pm_status pm_classify_scan_pack(pm_ctx *ctx, const pm_decomp *decomp, const pm_p
                                pm::kPrepZeroCounts | pm::kPrepCheckIn | pm::kPrepCheckSend,
                            st),
            "prep launch");
-    PM_HIP(pm::launch_classify(k, sh, mixed, persistent_grid(ctx, sh, mixed, false, false, false), st),
+    const int grid = persistent_grid(ctx, sh, mixed, false, false, false);
+    set_groups(ctx, k, grid);
+    PM_HIP(pm::launch_classify(k, sh, mixed, grid, st),
            "classify launch");
     PM_HIP(pm::launch_route(k, mixed, false, st), "route launch");
     return PM_OK;
@@ -627,10 +644,11 @@ static pm_status queue_stage(pm_ctx *ctx, pm::KArgs &k, bool mixed, int stage, p
     const int per = ctx->blocks_per_cu > 0
                         ? ctx->blocks_per_cu
                         : pm::stage_occupancy(sh, mixed, k.f.halo != 0, k.drag != 0, stage);
+    const int grid = std::max(1, ctx->cus * per);
+    set_groups(ctx, k, grid);
     if (timed)
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount], st), "event record");
-    PM_HIP(pm::launch_stage(k, sh, mixed, stage, std::max(1, ctx->cus * per), st),
-           "stage launch");
+    PM_HIP(pm::launch_stage(k, sh, mixed, stage, grid, st), "stage launch");
     if (timed) {
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount + 1], st), "event record");
         ctx->tcount++;
@@ -699,10 +717,11 @@ pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
     const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
     k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(k.sub_count);
-    std::vector<unsigned char> key(sizeof k + sizeof sh + sizeof(int));
+    std::vector<unsigned char> key(sizeof k + sizeof sh + 2 * sizeof(int));
     std::memcpy(key.data(), &k, sizeof k);
     std::memcpy(key.data() + sizeof k, &sh, sizeof sh);
     std::memcpy(key.data() + sizeof k + sizeof sh, &ctx->blocks_per_cu, sizeof(int));
+    std::memcpy(key.data() + sizeof k + sizeof sh + sizeof(int), &ctx->xcd_block, sizeof(int));
     for (auto &g : ctx->graphs)
         if (g.key == key) {
             PM_HIP(hipGraphLaunch(g.exec, st), "graph launch");
@@ -755,6 +774,9 @@ pm_status pm_set_tuning(pm_ctx *ctx, const pm_tuning *t)
         return arg_error("NULL argument");
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 32)
         return arg_error("blocks_per_cu out of range");
+    if (t->xcd_block < 0 || t->xcd_block > 65536)
+        return arg_error("xcd_block out of range");
+    ctx->xcd_block = t->xcd_block;
     if (t->wg == 0) {  // back to the per-variant defaults
         ctx->shape_auto = true;
         ctx->blocks_per_cu = t->blocks_per_cu;
@@ -777,7 +799,7 @@ pm_status pm_get_tuning(pm_ctx *ctx, pm_tuning *t)
     t->wg = sh.wg;
     t->items = sh.items;
     t->blocks_per_cu = ctx->blocks_per_cu;
-    t->pad_ = 0;
+    t->xcd_block = ctx->xcd_block;
     return PM_OK;
 }
 

@@ -820,6 +820,9 @@ __global__ __launch_bounds__(256) void k_prep(const KArgs a, int mode)
                         hdr[kHdrTiles] = (uint32_t)total;
                     }
                     hdr[kHdrTicket] = 0u;
+#pragma unroll
+                    for (int g = 0; g < kMaxGroups; ++g)
+                        hdr[kHdrGroupTicket + g] = 0u;
                 } else if (total > a.ws.stg_extent) {
                     bad |= PM_F_LAYOUT;
                 }
@@ -876,14 +879,35 @@ __global__ __launch_bounds__(256) void k_prep(const KArgs a, int mode)
 }
 
 // Take the next ticket and find its tile (thread 0); false when done.
+//
+// With xg > 1 ticket groups, workgroup b draws from the counter of group
+// b mod xg, and group g's n-th ticket is tile (n / xb) * xg * xb + g * xb +
+// n mod xb: the tile order is cut into blocks of xb consecutive tiles dealt
+// to the groups in turn.  A group is an XCD, so the tiles running at once
+// on one XCD are neighbours in the cell-sorted order and share their stencil
+// sectors in that XCD's L2, while all groups still move through the tile
+// order together.  No look-back waits forever: the lowest tile without an
+// aggregate is its group's next ticket, and every workgroup of that group is
+// at worst walking back over lower tiles, whose aggregates all come.  This
+// needs every group to have a running workgroup, which the in-order dispatch
+// of workgroups 0..xg-1 gives.
 template <int WG, int ITEMS>
 __device__ __forceinline__ bool next_tile(const KArgs &a, TileLds<WG, ITEMS> &L,
                                           int64_t total)
 {
     if (threadIdx.x == 0) {
-        const int64_t q = (int64_t)__hip_atomic_fetch_add(
-            a.ws.hdr + kHdrTicket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        L.h.q = q;
+        int64_t q;
+        if (a.xg > 1) {
+            const int g = (int)(blockIdx.x % (uint32_t)a.xg);
+            const int64_t n = (int64_t)__hip_atomic_fetch_add(
+                a.ws.hdr + kHdrGroupTicket + g, 1u, __ATOMIC_RELAXED,
+                __HIP_MEMORY_SCOPE_AGENT);
+            q = (n / a.xb) * ((int64_t)a.xg * a.xb) + (int64_t)g * a.xb + n % a.xb;
+        } else {
+            q = (int64_t)__hip_atomic_fetch_add(a.ws.hdr + kHdrTicket, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        }
+        L.h.q = q < total ? q : total;
         if (q < total)
             locate(a, a.tile, q, L.h);
     }

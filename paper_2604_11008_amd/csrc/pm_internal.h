@@ -21,7 +21,11 @@ constexpr uint32_t kMigrantSlot = 0xffffffffu;
 constexpr int kMinTile = 256;
 
 // Header words of the workspace.
-enum { kHdrFlags = 0, kHdrTicket = 1, kHdrTiles = 2, kHdrWords = 64 };
+enum { kHdrFlags = 0, kHdrTicket = 1, kHdrTiles = 2, kHdrGroupTicket = 32, kHdrWords = 64 };
+
+// Ticket groups of the tile kernels: one per XCD (workgroups are dispatched
+// to the XCDs round-robin, so workgroup b runs on XCD b mod 8).
+enum { kMaxGroups = 8 };
 
 struct DField {
     const void *u[3];
@@ -91,6 +95,7 @@ struct KArgs {
     float kappaf;
     int32_t sub_first, sub_count;
     int32_t tile;        // records per tile of this launch shape
+    int32_t xg, xb;      // ticket groups (<= 1: one global ticket), tiles per block
     int32_t cpt;         // append: workgroups per destination
 };
 

@@ -75,7 +75,7 @@ DRAG = {"stokes": 0, "nonlinear": 1}
 
 class _Tuning(C.Structure):
     _fields_ = [("wg", C.c_int32), ("items", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("xcd_block", C.c_int32)]
 
 
 _lib = None
@@ -426,14 +426,14 @@ class Context:
         _check(lib().pm_get_status(self.h, _stream(stream), C.byref(f)))
         return int(f.value)
 
-    def set_tuning(self, wg, items, blocks_per_cu=0):
-        t = _Tuning(wg, items, blocks_per_cu, 0)
+    def set_tuning(self, wg, items, blocks_per_cu=0, xcd_block=0):
+        t = _Tuning(wg, items, blocks_per_cu, xcd_block)
         _check(lib().pm_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self):
         t = _Tuning()
         _check(lib().pm_get_tuning(self.h, C.byref(t)))
-        return (t.wg, t.items, t.blocks_per_cu)
+        return (t.wg, t.items, t.blocks_per_cu, t.xcd_block)
 
     def autotune(self, field, decomp, pin, pout, send, params, cache_path=None, stream=None):
         pc = self._pool(pin, "in")

@@ -8,6 +8,11 @@ stage-2 stencils touch, and prints the sum over groups x 3 components x 64 B:
 the field bytes a cache that kept exactly one group's data would fetch.  The
 stage-2 position is X + dt U(X) with U from the oracle (the step starts from
 V = U(X)).  Compare with the measured FETCH_SIZE of the kernel.
+
+Then, per 64-lane gather instruction (one wave's 16-byte x-pair load of one
+stencil row of one component), the mean number of distinct 64-byte lines it
+touches, for the pool order and two other cell orders: the L1 tag lookups
+per gather that the kernel's TCP_TOTAL_CACHE_ACCESSES counts.
 """
 import os
 import sys
@@ -51,6 +56,24 @@ def main():
               f"({tot * 3 * 64 / np_:.1f} B/particle)")
     allu = np.unique(np.concatenate([s1.ravel(), s2.ravel()])).size
     print(f"whole step: {allu * 3 * 64 / 1e9:.3f} GB ({allu * 3 * 64 / np_:.1f} B/particle)")
+
+    cell = [np.clip(np.floor(x[a] * (n / L)).astype(np.int64), 0, n - 1) for a in range(3)]
+    orders = {
+        "pool order (Z-order over x-pairs)": np.arange(np_),
+        "Z-order of cells": np.argsort(gen.morton3(*cell), kind="stable"),
+        "Z-order over x-quads": np.argsort(gen.morton3(cell[0] >> 2, cell[1], cell[2]) * 4
+                                           + (cell[0] & 3), kind="stable"),
+    }
+    nw = np_ // 64
+    for name, perm in orders.items():
+        tot = 0
+        for s in (s1[:, perm], s2[:, perm]):
+            for r in range(4):  # stencil rows (dy, dz); each spans 1 or 2 sectors
+                ll = np.concatenate([s[2 * r, :nw * 64].reshape(nw, 64),
+                                     s[2 * r + 1, :nw * 64].reshape(nw, 64)], axis=1)
+                ll.sort(axis=1)
+                tot += (1 + (np.diff(ll, axis=1) != 0).sum(axis=1)).sum()
+        print(f"lines per gather instruction, {name}: {tot / (nw * 8):.1f}")
 
 
 if __name__ == "__main__":

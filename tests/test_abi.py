@@ -39,7 +39,7 @@ def header_layout(tmp_path):
         "pm_particles": ["nsub", "vdtype", "base", "cap", "count", "x", "v", "tau", "id"],
         "pm_sendbufs": ["base", "cap", "count", "x", "v", "tau", "id"],
         "pm_params": ["dt", "g", "drag", "nu", "density_ratio"],
-        "pm_tuning": ["wg", "items", "blocks_per_cu"],
+        "pm_tuning": ["wg", "items", "blocks_per_cu", "xcd_block"],
         "pm_stage_particles": ["nsub", "vdtype", "base", "cap", "count", "x", "v", "xs", "vs",
                                "a", "tau", "id"],
         "pm_stage_sendbufs": ["base", "cap", "count", "x", "v", "xs", "vs", "a", "tau", "id"],

@@ -255,9 +255,11 @@ def test_every_launch_shape_gives_identical_results():
     ref_out, ref_send = None, None
     ctx = c.ctx(pin, c.send())
     for wg, items in pm.SHAPES:
-        for bpc in (0, 1):
-            say(f"  shape wg={wg} items={items} bpc={bpc}")
-            ctx.set_tuning(wg, items, bpc)
+        # blocks per CU (0 = occupancy) and the tile order (0 = one ticket
+        # counter; 3, 16 = XCD-cyclic blocks of that many tiles)
+        for bpc, xb in ((0, 0), (1, 3), (0, 16)):
+            say(f"  shape wg={wg} items={items} bpc={bpc} xcd_block={xb}")
+            ctx.set_tuning(wg, items, bpc, xb)
             send, out = c.send(), c.pout(pin.size)
             ctx.step(c.field, c.dc, pin, out, send, c.params)
             assert ctx.get_status() == 0

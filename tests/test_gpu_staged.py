@@ -72,7 +72,8 @@ def test_staged_step_matches_oracle(name, npart, n, p, drag):
         f"max err x {ex:.2e} v {ev:.2e}")
 
 
-@pytest.mark.parametrize("shape", [(256, 1), (256, 4), (512, 2)])
+# (wg, items[, blocks per CU, XCD-cyclic tile blocks])
+@pytest.mark.parametrize("shape", [(256, 1), (256, 4), (512, 2), (256, 2, 0, 3)])
 def test_staged_step_is_shape_invariant(shape):
     say(f"[test] staged shapes {shape}")
     c = Case("C2S", 60000, 32, (4, 4, 4), face=0.2, edge=0.05, corner=0.03)
