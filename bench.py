@@ -72,7 +72,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain torch copy of 1 GiB (PMC scaling reference)")
+                    help="accepted for the profiling commands: the plain torch copy of "
+                         "1 GiB (the counters' scaling reference and the copy-rate "
+                         "figure) always runs")
     ap.add_argument("--traffic", default=None,
                     help="traffic record of the fused kernel (default: "
                          "profiles/k_step_<config>_traffic.json)")
@@ -114,9 +116,36 @@ def cpu_baseline(wl, seconds, drag="stokes", stagger=False, max_particles=1 << 2
     el = time.perf_counter() - t0
     what = (f"the first {npart} of {npart_all} particles (the same share of every segment)"
             if subset else f"all {npart} particles")
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f
+                          if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": done / el, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "host": {"cpu": model, "threads": os.cpu_count()},
             "sample": f"{steps} whole oracle step(s) of the same workload on {what}, "
                       f"sequential FP64, one thread, {el:.1f} s"}
+
+
+def copy_rate(dev, nbytes=1 << 30, reps=10):
+    """Milliseconds and GB/s (read + written) of a plain torch device copy of
+    nbytes; also the reference the counter runs are scaled by."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return ms, 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def single_core_triad_gbps(nbytes=1 << 28, reps=5):
@@ -400,21 +429,17 @@ def main():
         torch.cuda.synchronize()
         tq1 = time.perf_counter()
         extra["plain_per_subdomain_ms_per_step_incl_copy"] = round((tq1 - tq0) * 1e3 / steps, 4)
-    if args.copy_probe:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(10):
-            b.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        cms = e0.elapsed_time(e1) / 10
-        extra["copy_1GiB_ms"] = round(cms, 4)
-        extra["copy_GBps"] = round(2 * a.numel() * 8 / (cms * 1e-3) / 1e9, 1)
+    # a plain device copy of 1 GiB: the copy rate the kernel is also compared with
+    cms, copy_gbps = copy_rate(dev)
+    extra["copy_1GiB_ms"] = round(cms, 4)
+    extra["copy_GBps"] = round(copy_gbps, 1)
+    if roof is not None:
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbps, 4)
+        if roof["traffic"]:
+            # measured bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE) per kernel time
+            tr = roof["traffic"] / (roof["kernel_ms"] * 1e-3) / 1e9
+            roof["traffic_GBps"] = round(tr, 1)
+            roof["traffic_frac_of_copy"] = round(tr / copy_gbps, 4)
 
     cpu = None
     if not args.no_cpu:

@@ -3,8 +3,8 @@ that bench.py reports.
 
 Traffic of a kernel = FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two
 separate `rocprofv3 --pmc` runs, each scaled by what the same counter reads
-for a plain device copy of known size in the same run (bench.py
---copy-probe: torch copy of 1 GiB, i.e. 1 GiB read and 1 GiB written).  The
+for a plain device copy of known size in the same run (bench.py always
+runs a torch copy of 1 GiB, i.e. 1 GiB read and 1 GiB written).  The
 record carries a hash of the kernel sources and of the workload generator;
 once either changes, the record no longer applies and bench.py reports
 traffic as null.
