@@ -9,6 +9,8 @@ the field bytes a cache that kept exactly one group's data would fetch.  The
 stage-2 position is X + dt U(X) with U from the oracle (the step starts from
 V = U(X)).  Compare with the measured FETCH_SIZE of the kernel.
 
+The same for 128-byte lines (what the L2 fetches from memory per miss).
+
 Then, per 64-lane gather instruction (one wave's 16-byte x-pair load of one
 stencil row of one component), the mean number of distinct 64-byte lines it
 touches, for the pool order and two other cell orders: the L1 tag lookups
@@ -24,7 +26,8 @@ import oracle  # noqa: E402
 from paper_2604_11008_amd import gen  # noqa: E402
 
 
-def sectors(X, n, L, halo):
+def sectors(X, n, L, halo, line=64):
+    """Memory lines of `line` bytes that each stencil row's x pair touches."""
     S = n + 2 * halo
     s = X * (n / L) - 0.5
     i = np.floor(s).astype(np.int64) + halo
@@ -33,8 +36,8 @@ def sectors(X, n, L, halo):
         for dz in (0, 1):
             row = (i[1] + dy) + S * (i[2] + dz)
             b0 = (row * S + i[0]) * 8
-            out.append(b0 // 64)
-            out.append((b0 + 15) // 64)
+            out.append(b0 // line)
+            out.append((b0 + 15) // line)
     return np.stack(out)
 
 
@@ -56,13 +59,21 @@ def main():
               f"({tot * 3 * 64 / np_:.1f} B/particle)")
     allu = np.unique(np.concatenate([s1.ravel(), s2.ravel()])).size
     print(f"whole step: {allu * 3 * 64 / 1e9:.3f} GB ({allu * 3 * 64 / np_:.1f} B/particle)")
+    # the L2 fetches 128-byte lines from memory
+    t1, t2 = sectors(x, n, L, wl.halo, 128), sectors(xs, n, L, wl.halo, 128)
+    for G in (256, 1024):
+        tot = 0
+        for g0 in range(0, np_, G):
+            tot += np.unique(np.concatenate([t1[:, g0:g0 + G].ravel(),
+                                             t2[:, g0:g0 + G].ravel()])).size
+        print(f"groups of {G:5d}, 128-byte lines: {tot * 3 * 128 / 1e9:.3f} GB")
 
     cell = [np.clip(np.floor(x[a] * (n / L)).astype(np.int64), 0, n - 1) for a in range(3)]
     orders = {
-        "pool order (Z-order over x-pairs)": np.arange(np_),
+        "pool order (Z-order over 4-cell x runs)": np.arange(np_),
         "Z-order of cells": np.argsort(gen.morton3(*cell), kind="stable"),
-        "Z-order over x-quads": np.argsort(gen.morton3(cell[0] >> 2, cell[1], cell[2]) * 4
-                                           + (cell[0] & 3), kind="stable"),
+        "Z-order over x pairs": np.argsort(gen.morton3(cell[0] >> 1, cell[1], cell[2]) * 2
+                                           + (cell[0] & 1), kind="stable"),
     }
     nw = np_ // 64
     for name, perm in orders.items():
