@@ -392,11 +392,11 @@ def morton3(i, j, k, bits=11):
 
 
 def cell_key(i, j, k):
-    """Sort key of the canonical order: the Z-order code of (i/4, j, k), then
-    i mod 4, so that the smallest blocks are runs of four cells along x, the
-    axis along which a stencil row's nodes share memory lines."""
+    """Sort key of the canonical order: the Z-order code of (i/2, j, k), then
+    the parity of i, so that the smallest blocks are two cells long in x,
+    the axis along which a stencil's two nodes share memory sectors."""
     i = np.asarray(i, dtype=np.int64)
-    return morton3(i >> 2, j, k) * 4 + (i & 3)
+    return morton3(i >> 1, j, k) * 2 + (i & 1)
 
 
 def build_pool(pos, tau, ids, p, bnds, n, L=TWO_PI, slack=0.05, extra=1024,

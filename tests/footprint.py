@@ -70,10 +70,10 @@ def main():
 
     cell = [np.clip(np.floor(x[a] * (n / L)).astype(np.int64), 0, n - 1) for a in range(3)]
     orders = {
-        "pool order (Z-order over 4-cell x runs)": np.arange(np_),
+        "pool order (Z-order over x pairs)": np.arange(np_),
         "Z-order of cells": np.argsort(gen.morton3(*cell), kind="stable"),
-        "Z-order over x pairs": np.argsort(gen.morton3(cell[0] >> 1, cell[1], cell[2]) * 2
-                                           + (cell[0] & 1), kind="stable"),
+        "Z-order over 4-cell x runs": np.argsort(gen.morton3(cell[0] >> 2, cell[1], cell[2])
+                                                 * 4 + (cell[0] & 3), kind="stable"),
     }
     nw = np_ // 64
     for name, perm in orders.items():

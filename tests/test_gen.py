@@ -64,16 +64,16 @@ def test_pool_layout_and_canonical_order():
         assert np.all(np.diff(key) >= 0)
 
 
-def test_cell_key_orders_x_runs_then_z_order():
-    i, j, k = np.meshgrid(np.arange(8), np.arange(2), np.arange(2), indexing="ij")
+def test_cell_key_orders_x_pairs_then_z_order():
+    i, j, k = np.meshgrid(np.arange(4), np.arange(2), np.arange(2), indexing="ij")
     i, j, k = i.ravel(), j.ravel(), k.ravel()
     order = np.argsort(gen.cell_key(i, j, k), kind="stable")
     cells = list(zip(i[order], j[order], k[order]))
-    # runs of four cells along x are the leaves; the runs follow the Z-order
-    # of (i/4, j, k): run 0, run 1, then j, then k
-    assert cells[:8] == [(x, 0, 0) for x in range(8)]
-    assert cells[8:16] == [(x, 1, 0) for x in range(8)]
-    assert cells[16:20] == [(x, 0, 1) for x in range(4)]
+    # x pairs are the leaves; the pairs themselves follow the Z-order of
+    # (i/2, j, k): x pair 0, x pair 1, then j, then k
+    assert cells[:4] == [(0, 0, 0), (1, 0, 0), (2, 0, 0), (3, 0, 0)]
+    assert cells[4:8] == [(0, 1, 0), (1, 1, 0), (2, 1, 0), (3, 1, 0)]
+    assert cells[8:10] == [(0, 0, 1), (1, 0, 1)]
     assert len(set(gen.cell_key(i, j, k))) == i.size
 
 
