@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--order", default="canonical",
+                    choices=["canonical", "morton", "rowmajor", "shuffled"],
+                    help="particle order within each segment at the start: cell-sorted "
+                         "(canonical: Z-order over x pairs; morton; rowmajor) or shuffled")
     ap.add_argument("--precision", default="auto", choices=["auto", "f64", "mixed"],
                     help="override the workload's arithmetic (mixed: float32 field, "
                          "velocities and tau; float64 positions)")
@@ -205,7 +209,8 @@ def main():
     multi = np.prod(gen.CONFIGS[args.config]["p"]) > 1
     # subdomain counts random-walk as particles migrate: leave room to grow
     wl = gen.make_workload(args.config, field_backend="device" if big else "numpy",
-                           slack=0.25 if multi else 0.05, extra=4096 if multi else 1024)
+                           slack=0.25 if multi else 0.05, extra=4096 if multi else 1024,
+                           order=args.order)
     t_gen = time.perf_counter() - t_gen
     mixed = wl.mode == "mixed" if args.precision == "auto" else args.precision == "mixed"
     if mixed != (wl.mode == "mixed"):
@@ -314,8 +319,9 @@ def main():
         tpath = args.traffic or os.path.join(ROOT, "profiles",
                                              f"k_step_{args.config}_traffic.json")
         traffic = None
+        # the record was taken on the canonical start order of this workload
         if os.path.exists(tpath) and json.load(open(tpath)).get("kernel") == variant \
-                and not args.staged:
+                and not args.staged and args.order == "canonical":
             traffic = profsum.load_traffic(tpath)
         roof = {"bound": "hbm", "achieved": round(achieved, 1),
                 "peak": accounting.HBM_PEAK_GBPS, "unit": "GB/s",
@@ -466,7 +472,8 @@ def main():
                    (", migration after each RK2 stage" if args.staged else "") +
                    (f" (run at {args.precision})" if args.precision != "auto" else "") +
                    (", nonlinear drag" if args.drag == "nonlinear" else "") +
-                   (", MAC-staggered field" if args.stagger else ""),
+                   (", MAC-staggered field" if args.stagger else "") +
+                   (f", {args.order} particle order" if args.order != "canonical" else ""),
                    "particles": npart, "grid": wl.n, "halo": wl.halo,
                    "subdomains": list(wl.p), "graph": bool(args.graph),
                    "tuning": list(ctx.get_tuning())},
