@@ -126,3 +126,21 @@ def assert_same_device_pools(a, b, nseg, what):
         for name in ("x", "v", "tau", "id"):
             np.testing.assert_array_equal(getattr(ha, name)[..., s], getattr(hb, name)[..., s],
                                           err_msg=f"{what} {name} seg {q}")
+
+
+def compare_mid(got, ref, nseg, L, delta, what):
+    """Counts, ids and order exactly; X_n, X* to 1e-12 of max(|x|, cell);
+    V_n, V*, a to 1e-12 of max(|ref|, 1)."""
+    np.testing.assert_array_equal(got.count, ref.count, err_msg=f"{what} counts")
+    for q in range(nseg):
+        b, c = int(ref.base[q]), int(min(ref.count[q], ref.cap[q]))
+        s = slice(b, b + c)
+        np.testing.assert_array_equal(got.id[s], ref.id[s], err_msg=f"{what} ids seg {q}")
+        for name in ("x", "xs"):
+            g, r = getattr(got, name)[:, s], getattr(ref, name)[:, s]
+            e = np.abs(g - r) / np.maximum(np.abs(r), delta)
+            assert e.size == 0 or e.max() <= 1e-12, (what, name, q, e.max())
+        for name in ("v", "vs", "a"):
+            g, r = getattr(got, name)[:, s].astype(np.float64), getattr(ref, name)[:, s]
+            e = np.abs(g - r) / max(1.0, float(np.abs(r).max()) if r.size else 1.0)
+            assert e.size == 0 or e.max() <= 1e-12, (what, name, q, e.max())

@@ -5,13 +5,17 @@ gravity) and the same field cut into 8x8x8 periodic subdomains with a few
 percent migrating per step: one fused step on the GPU against one whole
 step of the CPU oracle on the same seeded input (the oracle runs in a few
 seconds at this size).  Counts, ids and their order must match exactly;
-positions and velocities to 1e-12.
+positions and velocities to 1e-12.  The same at full size for the nonlinear
+drag law, the MAC-staggered field and migration after each RK2 stage (its
+mid-step pool and send buffers too), each in its default launch shape.
 """
 import numpy as np
 import pytest
 import torch
 
-from gpu_cases import Case, compare_pools, say
+import oracle
+from gpu_cases import Case, compare_mid, compare_pools, say
+from paper_2604_11008_amd import gen, pm
 
 pytestmark = pytest.mark.gpu
 
@@ -43,3 +47,53 @@ def test_full_size_step_matches_the_oracle(name, shape):
     compare_pools(send.to_host(), ref_send, c.dc.nsub * 27, c.wl.L, delta, what="send")
     ex, ev = compare_pools(pout.to_host(), ref_out, c.dc.nsub, c.wl.L, delta, what="out")
     say(f"  migrants {int(ref_send.count.sum())}; max rel err x {ex:.2e} v {ev:.2e}")
+
+
+@pytest.mark.parametrize("name,drag,stagger", [("C2", "nonlinear", False),
+                                               ("C2S", "stokes", True)])
+def test_full_size_variant_matches_the_oracle(name, drag, stagger):
+    say(f"[test] full-size {name} drag={drag} stagger={stagger}")
+    c = Case(name, face=0.05, edge=0.01, corner=0.005, drag=drag, stagger=stagger)
+    if name == "C2S":
+        c.params.dt = min(c.dt, 0.015)
+    pin, send = c.pin(), c.send()
+    pout = c.pout(pin.size)
+    ctx = c.ctx(pin, send)
+    ctx.step(c.field, c.dc, pin, pout, send, c.params)
+    flags = ctx.get_status()
+    say(f"  gpu flags {flags}, shape {ctx.get_tuning()}")
+    ref_out, ref_send, _, oflags = c.oracle_step(dt=c.params.dt)
+    assert flags == oflags == 0
+    delta = c.wl.L / c.wl.n
+    compare_pools(send.to_host(), ref_send, c.dc.nsub * 27, c.wl.L, delta, what="send")
+    ex, ev = compare_pools(pout.to_host(), ref_out, c.dc.nsub, c.wl.L, delta, what="out")
+    say(f"  migrants {int(ref_send.count.sum())}; max rel err x {ex:.2e} v {ev:.2e}")
+
+
+@pytest.mark.parametrize("name", ["C2", "C2S"])
+def test_full_size_staged_step_matches_the_oracle(name):
+    say(f"[test] full-size staged {name}")
+    c = Case(name, face=0.05, edge=0.01, corner=0.005)
+    if name == "C2S":
+        c.params.dt = min(c.dt, 0.015)
+    pin, send = c.pin(), c.send()
+    pout = c.pout(pin.size)
+    mid = pm.DeviceStagePool.empty(c.host.base, c.host.cap, device=c.dev, size=pin.size)
+    msend = pm.DeviceStagePool.empty(c.sb, c.sc, device=c.dev, size=send.size)
+    ctx = c.ctx(pin, send)
+    ctx.step_staged(c.field, c.dc, pin, mid, msend, pout, send, c.params)
+    flags = ctx.get_status()
+    say(f"  gpu flags {flags}, shape {ctx.get_tuning()}")
+    rmid = gen.empty_stage_pool(c.host.base, c.host.cap)
+    rms = gen.empty_stage_pool(c.sb, c.sc)
+    rout, rsend = gen.empty_pool(c.host.base, c.host.cap), gen.empty_pool(c.sb, c.sc)
+    oflags = oracle.step_staged(c.ofield, c.odc, c.params.dt, c.g, c.host, rmid, rms, rout,
+                                rsend)
+    assert flags == oflags == 0
+    delta = c.wl.L / c.wl.n
+    compare_mid(msend.to_host(), rms, c.dc.nsub * 27, c.wl.L, delta, "mid_send")
+    compare_mid(mid.to_host(), rmid, c.dc.nsub, c.wl.L, delta, "mid")
+    compare_pools(send.to_host(), rsend, c.dc.nsub * 27, c.wl.L, delta, what="send")
+    ex, ev = compare_pools(pout.to_host(), rout, c.dc.nsub, c.wl.L, delta, what="out")
+    say(f"  stage-1 migrants {int(rms.count.sum())}, stage-2 {int(rsend.count.sum())}; "
+        f"max rel err x {ex:.2e} v {ev:.2e}")

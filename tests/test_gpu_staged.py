@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_cases import Case, compare_pools, say
+from gpu_cases import Case, compare_mid, compare_pools, say
 from paper_2604_11008_amd import gen, pm
 
 pytestmark = pytest.mark.gpu
@@ -18,24 +18,6 @@ pytestmark = pytest.mark.gpu
 def _need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-
-
-def compare_mid(got, ref, nseg, L, delta, what):
-    """Counts, ids and order exactly; X_n, X* to 1e-12 of max(|x|, cell);
-    V_n, V*, a to 1e-12 of max(|ref|, 1)."""
-    np.testing.assert_array_equal(got.count, ref.count, err_msg=f"{what} counts")
-    for q in range(nseg):
-        b, c = int(ref.base[q]), int(min(ref.count[q], ref.cap[q]))
-        s = slice(b, b + c)
-        np.testing.assert_array_equal(got.id[s], ref.id[s], err_msg=f"{what} ids seg {q}")
-        for name in ("x", "xs"):
-            g, r = getattr(got, name)[:, s], getattr(ref, name)[:, s]
-            e = np.abs(g - r) / np.maximum(np.abs(r), delta)
-            assert e.size == 0 or e.max() <= 1e-12, (what, name, q, e.max())
-        for name in ("v", "vs", "a"):
-            g, r = getattr(got, name)[:, s].astype(np.float64), getattr(ref, name)[:, s]
-            e = np.abs(g - r) / max(1.0, float(np.abs(r).max()) if r.size else 1.0)
-            assert e.size == 0 or e.max() <= 1e-12, (what, name, q, e.max())
 
 
 CASES = [("C1", None, None, None), ("C2", 40000, 32, None), ("C2S", 60000, 32, (4, 4, 4)),
