@@ -74,6 +74,12 @@ def parse():
     ap.add_argument("--tune", default=None, help="wg,items[,blocks_per_cu[,xcd_block]] or 'auto'")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="also run --accuracy-steps untimed steps from the start state and "
+                         "report the error of the particles with the lowest ids against "
+                         "the FP64 oracle after the first and the last")
+    ap.add_argument("--accuracy-sample", type=int, default=1 << 20)
+    ap.add_argument("--accuracy-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="accepted for the profiling commands: the plain torch copy of "
@@ -90,6 +96,92 @@ def parse():
     return ap.parse_args()
 
 
+def host_field64(wl):
+    """The stored field as float64 numpy arrays (copied off the device when the
+    field was generated there)."""
+    return [u if isinstance(u, np.ndarray) else u.cpu().numpy()
+            for u in wl.stored_field(np.float64)]
+
+
+def subsample(p, nmax):
+    """Valid records of device pool p whose id is below nmax, sorted by id, on
+    the host as float64 (x, v, tau, id)."""
+    import torch
+    size = p.x.shape[1]
+    valid = torch.zeros(size, dtype=torch.bool, device=p.x.device)
+    base, count = p.base.cpu().numpy(), p.count.cpu().numpy()
+    for b, c in zip(base, count):
+        if c > 0:
+            valid[int(b):int(b) + int(c)] = True
+    sel = torch.nonzero(valid & (p.id < nmax)).squeeze(1)
+    ids = p.id[sel]
+    order = torch.argsort(ids)
+    sel = sel[order]
+    return (p.x[:, sel].cpu().numpy(), p.v[:, sel].double().cpu().numpy(),
+            p.tau[sel].double().cpu().numpy(), p.id[sel].cpu().numpy().astype(np.uint64))
+
+
+def accuracy_report(wl, field, dc, ctx, params, pstart, pool_template, sb, sc, vdt, dev,
+                    nmax, steps, drag):
+    """Untimed: `steps` device steps from pstart on spare pools, and the oracle
+    in FP64 (the float64 field) on the particles with id < nmax from the same
+    start state (float64 positions; velocities and tau as the device holds
+    them).  Particles do not interact, so the oracle follows the subsample
+    alone, in one periodic subdomain.  Errors: max |dV| / max|u| and max |dX|
+    in cells (across the periodic seam), after the first and the last step."""
+    import oracle
+    from paper_2604_11008_amd import pm
+    qa = pm.DevicePool(pstart.x.clone(), pstart.v.clone(), pstart.tau.clone(),
+                       pstart.id.clone(), pstart.base, pstart.cap, pstart.count.clone())
+    qb = pm.DevicePool.empty(pool_template.base, pool_template.cap, vdtype=vdt, device=dev,
+                             size=pstart.x.shape[1])
+    qsend = pm.DevicePool.empty(sb, sc, vdtype=vdt, device=dev)
+    x0, v0, tau0, id0 = subsample(qa, nmax)
+    got = {}
+    for k in range(1, steps + 1):
+        ctx.step(field, dc, qa, qb, qsend, params)
+        qa, qb = qb, qa
+        if k in (1, steps):
+            got[k] = subsample(qa, nmax)
+    f = ctx.get_status()
+    if f:
+        raise SystemExit(f"accuracy run flags: {pm.flag_names(f)}")
+    del qa, qb, qsend
+    fh = host_field64(wl)
+    umax = max(float(np.abs(u).max()) for u in fh)
+    of = oracle.Field(fh, wl.n, wl.halo, wl.L)
+    od = oracle.Decomp((1, 1, 1), gen.bounds((1, 1, 1), wl.L))
+    m = len(id0)
+    cap = np.array([m + 1024], dtype=np.int64)
+    host = gen.empty_pool(np.zeros(1, dtype=np.int64), cap)
+    host.x[:, :m], host.v[:, :m], host.tau[:m], host.id[:m] = x0, v0, tau0, id0
+    host.count[0] = m
+    osb, osc = gen.send_layout(host.count, face=0.2, edge=0.05, corner=0.03)
+    out = {"subsample": m, "ids": f"below {nmax}", "steps": steps,
+           "oracle": "FP64 on the float64 field, one periodic subdomain"}
+    cell = wl.n / wl.L
+    for k in range(1, steps + 1):
+        nxt = gen.empty_pool(host.base, host.cap)
+        send = gen.empty_pool(osb, osc)
+        _, fl = oracle.step(of, od, params.dt, params.g, host, nxt, send, drag=drag,
+                            nu=params.nu, density_ratio=params.density_ratio)
+        if fl:
+            raise SystemExit(f"oracle flags {fl} in the accuracy run")
+        host = nxt
+        if k in got:
+            c = int(host.count[0])
+            o = np.argsort(host.id[:c], kind="stable")
+            rx, rv, rid = host.x[:, :c][:, o], host.v[:, :c][:, o], host.id[:c][o]
+            gx, gv, _, gid = got[k]
+            if not np.array_equal(rid, gid):
+                raise SystemExit("accuracy run: the device and the oracle hold different ids")
+            dx = np.abs(gx - rx)
+            dx = np.minimum(dx, wl.L - dx)
+            out[f"after_{k}"] = {"v_err_rel_umax": float(np.abs(gv - rv).max() / umax),
+                                 "x_err_cells": float(dx.max() * cell)}
+    return out
+
+
 def cpu_baseline(wl, seconds, drag="stokes", stagger=False, max_particles=1 << 22):
     """The oracle, single-threaded, on whole steps of the same workload for
     about `seconds`.  Workloads above max_particles run on the first
@@ -102,7 +194,7 @@ def cpu_baseline(wl, seconds, drag="stokes", stagger=False, max_particles=1 << 2
     if subset:
         pool = gen.Pool(x=pool.x, v=pool.v, tau=pool.tau, id=pool.id, base=pool.base,
                         cap=pool.cap, count=pool.count * max_particles // npart_all)
-    of = oracle.Field(wl.stored_field(np.float64), wl.n, wl.halo, wl.L, stagger=stagger)
+    of = oracle.Field(host_field64(wl), wl.n, wl.halo, wl.L, stagger=stagger)
     od = oracle.Decomp(wl.p, wl.bounds)
     sb, sc = gen.send_layout(pool.count, face=0.05, edge=0.01, corner=0.005)
     npart = int(pool.count.sum())
@@ -234,6 +326,15 @@ def main():
     # v0 = U(x0), interpolated on the device
     pa.v.copy_(ctx.interp(field, pa.x))
     params = pm.Params(wl.dt, wl.g, drag=args.drag)
+    accuracy = None
+    if args.accuracy:
+        if args.staged or args.stagger:
+            raise SystemExit("--accuracy runs the per-step path on collocated fields")
+        ta = time.perf_counter()
+        accuracy = accuracy_report(wl, field, dc, ctx, params, pa, pool, sb, sc, vdt, dev,
+                                   args.accuracy_sample, args.accuracy_steps, args.drag)
+        print(f"[bench] accuracy run {time.perf_counter() - ta:.1f} s: {accuracy}",
+              file=sys.stderr, flush=True)
     mid = msend = None
     if args.staged:
         if args.graph or args.tune == "auto" or args.stagger:
@@ -481,6 +582,7 @@ def main():
         "algorithmic_bytes_per_step": alg["step"], "touched_nodes": touched,
         "migrants_per_step": migrants,
         "roofline": roof, "cpu_baseline": cpu,
+        **({"accuracy": accuracy} if accuracy is not None else {}),
     }
     line.update(extra)
     print(json.dumps(line), flush=True)
