@@ -283,8 +283,8 @@ def link_gbps(torch, dev, nbytes=1 << 28):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
-              "supported (subdomains are virtual partitions of one device)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(subdomains are virtual partitions of one device)", file=sys.stderr)
         sys.exit(2)
 
     import torch

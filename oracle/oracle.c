@@ -5,9 +5,9 @@
  * blocking, fusion or reordering.  Build with -O2 -ffp-contract=off so that
  * every product and sum rounds on its own, exactly as written.
  *
- * Readings of points the paper leaves open (each also listed in the design doc):
- *  R1  RK2 tableau: Heun (explicit trapezoid).  Sect. 2.2 names only "two-stage,
- *      second-order".
+ * Readings of points the paper leaves open:
+ *  R1  RK2 tableau: Heun (explicit trapezoid).  Sect. 2.2 gives only the number
+ *      of stages (two) and the order (second).
  *  R2  Drag factor f = 1 (Stokes); a constant body force g is added to dV/dt.
  *  R3  Nodes are collocated at cell centres (i+1/2)*Delta; weights use the
  *      fraction of s = X*(n/L) - 1/2 above floor(s).

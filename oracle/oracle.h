@@ -17,7 +17,7 @@
  *     f = 1 + 0.15 Re_p^0.687, Re_p = 2r|V - U(X)|/nu, with the radius r
  *     from tau = (2/9)(rho_p/rho)(r^2/nu) (Sect. 2.2);
  *   - the boundary-crossing check of each particle against its subdomain
- *     (Sect. 2.3.3, stage 1, "mask"), generalised to the 26 neighbours;
+ *     (Sect. 2.3.3, stage 1: the mask), generalised to the 26 neighbours;
  *   - the sequential per-direction-counter partition of the original
  *     Fortran LCS (Sect. 2.3.3, the sequential scheme), which the prefix-scan
  *     method reproduces exactly;
