@@ -293,11 +293,15 @@ pm_status pm_get_status(pm_ctx *ctx, void *stream, uint32_t *flags);
 pm_status pm_set_tuning(pm_ctx *ctx, const pm_tuning *t);
 pm_status pm_get_tuning(pm_ctx *ctx, pm_tuning *t);
 
-/* Time every supported launch shape on this problem with pm_step (eager),
- * keep the fastest in the context and, if cache_path is not NULL, append
- * it to that text file keyed by the problem's shape.  Results do not
- * depend on the launch shape.  Synchronous; in is unchanged, out and send
- * are overwritten. */
+/* Time every supported launch shape and workgroups-per-CU setting on this
+ * problem with pm_step (eager), keep the fastest in the context and, if
+ * cache_path is not NULL, append it to that text file keyed by the problem
+ * (grid, halo, element type, field arrangement, drag law, subdomain count,
+ * pool extent, tile order).  With a cache_path whose file already holds the
+ * key, take that entry and time nothing.  Results do not depend on the
+ * launch shape.  Synchronous; in is unchanged, out and send are
+ * overwritten.  On an error the context's tuning, graph and timing settings
+ * are as before the call. */
 pm_status pm_autotune(pm_ctx *ctx, const pm_field *field,
                       const pm_decomp *decomp, const pm_particles *in,
                       pm_particles *out, pm_sendbufs *send,

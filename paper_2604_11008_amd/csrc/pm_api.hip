@@ -848,6 +848,38 @@ pm_status pm_kernel_times(pm_ctx *ctx, int32_t *n, double *total_ms, float *ms, 
     return PM_OK;
 }
 
+// Context settings that a tuning sweep changes, put back on every way out of
+// pm_autotune unless the sweep finished and chose new ones.
+struct TuneGuard {
+    pm_ctx *ctx;
+    pm::Shape shape;
+    bool shape_auto;
+    int bpc;
+    bool graph;
+    int32_t tmax;
+    bool commit = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    explicit TuneGuard(pm_ctx *c)
+        : ctx(c), shape(c->shape), shape_auto(c->shape_auto), bpc(c->blocks_per_cu),
+          graph(c->use_graph), tmax(c->tmax)
+    {
+    }
+    ~TuneGuard()
+    {
+        if (!commit) {
+            ctx->shape = shape;
+            ctx->shape_auto = shape_auto;
+            ctx->blocks_per_cu = bpc;
+        }
+        ctx->use_graph = graph;
+        ctx->tmax = tmax;
+        if (e0)
+            (void)hipEventDestroy(e0);
+        if (e1)
+            (void)hipEventDestroy(e1);
+    }
+};
+
 pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
                       const pm_particles *in, pm_particles *out, pm_sendbufs *send,
                       const pm_params *params, void *stream, const char *cache_path)
@@ -858,10 +890,13 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
     if (s)
         return s;
     hipStream_t st = (hipStream_t)stream;
-    char key[256];
-    snprintf(key, sizeof key, "n=%d,%d,%d halo=%d dtype=%d nsub=%d extent=%lld",
-             field->n[0], field->n[1], field->n[2], field->halo, field->dtype, k.dc.nsub,
-             (long long)ctx->ws.pool_extent);
+    // everything the fastest shape depends on: grid, field arrangement and
+    // precision, drag law, decomposition, pool extent, tile order
+    char key[320];
+    snprintf(key, sizeof key,
+             "n=%d,%d,%d halo=%d dtype=%d stagger=%d drag=%d nsub=%d extent=%lld xcd=%d",
+             field->n[0], field->n[1], field->n[2], field->halo, field->dtype, field->stagger,
+             params->drag, k.dc.nsub, (long long)ctx->ws.pool_extent, ctx->xcd_block);
     if (cache_path) {
         if (FILE *fp = fopen(cache_path, "r")) {
             char line[512];
@@ -878,7 +913,7 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
                 }
             }
             fclose(fp);
-            if (hit && pm::shape_supported({wg, items})) {
+            if (hit && pm::shape_supported({wg, items}) && bpc >= 0 && bpc <= 32) {
                 ctx->shape = {wg, items};
                 ctx->shape_auto = false;
                 ctx->blocks_per_cu = bpc;
@@ -889,13 +924,11 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
     const pm::Shape shapes[] = {{256, 1}, {256, 2}, {256, 4}, {256, 8},
                                 {512, 1}, {512, 2}, {512, 4}};
     const int bpcs[] = {0, 2, 3, 4, 6};
-    const bool was_graph = ctx->use_graph;
-    const int32_t was_tmax = ctx->tmax;
+    TuneGuard guard(ctx);
     ctx->use_graph = false;
     ctx->tmax = 0;
-    hipEvent_t e0, e1;
-    PM_HIP(hipEventCreate(&e0), "event create");
-    PM_HIP(hipEventCreate(&e1), "event create");
+    PM_HIP(hipEventCreate(&guard.e0), "event create");
+    PM_HIP(hipEventCreate(&guard.e1), "event create");
     float best = 1e30f;
     pm::Shape best_sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
     int best_bpc = ctx->blocks_per_cu;
@@ -905,19 +938,22 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
             ctx->shape = sh;
             ctx->blocks_per_cu = bpc;
             pm::KArgs kk = k;
-            pm_status r = PM_OK;
-            for (int it = 0; it < 2 && !r; ++it)
-                r = queue_step(ctx, kk, mixed, st, false);
-            PM_HIP(hipEventRecord(e0, st), "event record");
+            for (int it = 0; it < 2; ++it) {
+                const pm_status r = queue_step(ctx, kk, mixed, st, false);
+                if (r)
+                    return r;
+            }
+            PM_HIP(hipEventRecord(guard.e0, st), "event record");
             const int reps = 5;
-            for (int it = 0; it < reps && !r; ++it)
-                r = queue_step(ctx, kk, mixed, st, false);
-            PM_HIP(hipEventRecord(e1, st), "event record");
-            PM_HIP(hipEventSynchronize(e1), "event sync");
-            if (r)
-                return r;
+            for (int it = 0; it < reps; ++it) {
+                const pm_status r = queue_step(ctx, kk, mixed, st, false);
+                if (r)
+                    return r;
+            }
+            PM_HIP(hipEventRecord(guard.e1, st), "event record");
+            PM_HIP(hipEventSynchronize(guard.e1), "event sync");
             float ms = 0.f;
-            PM_HIP(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            PM_HIP(hipEventElapsedTime(&ms, guard.e0, guard.e1), "elapsed");
             ms /= reps;
             if (getenv("PM_TUNE_VERBOSE"))
                 fprintf(stderr, "pm_autotune: wg=%d items=%d bpc=%d %.4f ms/step\n", sh.wg,
@@ -929,12 +965,9 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     ctx->shape = best_sh;
     ctx->blocks_per_cu = best_bpc;
-    ctx->use_graph = was_graph;
-    ctx->tmax = was_tmax;
+    guard.commit = true;
     if (cache_path) {
         if (FILE *fp = fopen(cache_path, "a")) {
             fprintf(fp, "%s| wg=%d items=%d bpc=%d ms=%.4f\n", key, best_sh.wg, best_sh.items,
