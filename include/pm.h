@@ -233,8 +233,10 @@ typedef struct pm_ctx pm_ctx;
  * pool_extent records (max over segments of base+cap), send buffers of at
  * most send_extent records, and nsub subdomains.  It holds, besides small
  * tables, one look-back word per tile, one slot per pool record for the
- * plain path, and a staging area of send_extent leaver records (65 bytes
- * each).  0 for invalid sizes. */
+ * plain path, and a staging area of send_extent leaver records (137 bytes
+ * each: the 17 eight-byte values of a mid-step record of per-stage
+ * migration, of which a per-step leaver uses 8, plus a direction byte).
+ * 0 for invalid sizes. */
 size_t pm_workspace_bytes(int64_t pool_extent, int64_t send_extent, int32_t nsub);
 
 /* Create a context on the current device.  workspace: caller-owned device
