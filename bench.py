@@ -337,8 +337,8 @@ def main():
               file=sys.stderr, flush=True)
     mid = msend = None
     if args.staged:
-        if args.graph or args.tune == "auto" or args.stagger:
-            raise SystemExit("--staged runs eager, without the autotuner, on collocated fields")
+        if args.tune == "auto" or args.stagger:
+            raise SystemExit("--staged runs without the autotuner, on collocated fields")
         mid = pm.DeviceStagePool.empty(pool.base, pool.cap, vdtype=vdt, device=dev, size=size)
         msend = pm.DeviceStagePool.empty(sb, sc, vdtype=vdt, device=dev, size=send.size)
 
@@ -472,7 +472,7 @@ def main():
             "compact_append": round(e[1].elapsed_time(e[2]) / reps, 4),
             "migrants": int(sendm.count.sum().item())}
         del sendm, outm, work
-    if not args.graph and not args.staged:
+    if not args.graph:
         # the same steps replayed from captured HIP graphs (two graphs: A->B, B->A)
         ctx.set_timing(0)
         ctx.set_graph(True)
@@ -481,12 +481,12 @@ def main():
         for t, v in zip((pa.x, pa.v, pa.tau, pa.id, pa.count), snap):
             t.copy_(v)
         for _ in range(2):
-            ctx.step(field, dc, pa, pb, send, params)
+            do_step(pa, pb)
             pa, pb = pb, pa
         torch.cuda.synchronize()
         tg0 = time.perf_counter()
         for _ in range(args.steps):
-            ctx.step(field, dc, pa, pb, send, params)
+            do_step(pa, pb)
             pa, pb = pb, pa
         torch.cuda.synchronize()
         tg1 = time.perf_counter()

@@ -310,7 +310,9 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field,
                       const pm_params *params, void *stream,
                       const char *cache_path);
 
-/* Capture pm_step into HIP graphs (enable != 0) or launch eagerly. */
+/* Capture pm_step and pm_step_staged into HIP graphs (enable != 0), one per
+ * distinct argument set, launch shape and tuning (at most 16 kept), and
+ * replay them; or launch eagerly (0). */
 pm_status pm_set_graph(pm_ctx *ctx, int32_t enable);
 
 /* Kernel timing: with max_records > 0, every eager pm_step records HIP
@@ -332,9 +334,9 @@ pm_status pm_kernel_times(pm_ctx *ctx, int32_t *n, double *total_ms, float *ms,
  * `send`).  Each exchange is the same scan, pack, compact and append as
  * pm_step's.  Collocated fields only; `in` is unchanged; mid must fit the
  * context's pool extent and mid_send its send extent.  Launch shapes with
- * at most 1024 records per tile (default 256 x 2).  Always launched eagerly
- * (pm_set_graph applies to pm_step); pm_set_timing records both stages'
- * fused kernels. */
+ * at most 1024 records per tile (default 256 x 2).  Replayed as one HIP
+ * graph of both stages under pm_set_graph, like pm_step; eager launches
+ * record both stages' fused kernels under pm_set_timing. */
 pm_status pm_step_staged(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
                          const pm_particles *in, pm_stage_particles *mid,
                          pm_stage_sendbufs *mid_send, pm_particles *out,

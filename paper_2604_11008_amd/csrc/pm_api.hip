@@ -359,6 +359,64 @@ void base_args(pm_ctx *ctx, pm::KArgs &k)
     k.ws = ctx->ws;
 }
 
+// Launch the graph captured for `key` on `st`, capturing it first (from what
+// `queue` enqueues on the context's capture stream) if this key is new.  At
+// most 16 graphs are kept, the oldest dropped first.
+template <typename Queue>
+pm_status run_captured(pm_ctx *ctx, const std::vector<unsigned char> &key,
+                              hipStream_t st, Queue queue)
+{
+    for (auto &g : ctx->graphs)
+        if (g.key == key) {
+            PM_HIP(hipGraphLaunch(g.exec, st), "graph launch");
+            return PM_OK;
+        }
+    if (!ctx->cap_stream)
+        PM_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "stream create");
+    PM_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal),
+           "begin capture");
+    const pm_status qs = queue(ctx->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (qs) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return qs;
+    }
+    if (ce != hipSuccess)
+        return hip_error(ce, "end capture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess)
+        return hip_error(ie, "graph instantiate");
+    if (ctx->graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back({key, exec});
+    PM_HIP(hipGraphLaunch(exec, st), "graph launch");
+    return PM_OK;
+}
+
+// Graph key: a tag, the launch arguments, the shape and the tuning that
+// decides the grid and the tile order.
+std::vector<unsigned char> graph_key(const pm_ctx *ctx, char tag,
+                                            const pm::KArgs *ks, int nk, pm::Shape sh)
+{
+    std::vector<unsigned char> key(1 + nk * sizeof(pm::KArgs) + sizeof sh + 2 * sizeof(int));
+    unsigned char *p = key.data();
+    *p++ = (unsigned char)tag;
+    for (int i = 0; i < nk; ++i, p += sizeof(pm::KArgs))
+        std::memcpy(p, &ks[i], sizeof(pm::KArgs));
+    std::memcpy(p, &sh, sizeof sh);
+    p += sizeof sh;
+    std::memcpy(p, &ctx->blocks_per_cu, sizeof(int));
+    p += sizeof(int);
+    std::memcpy(p, &ctx->xcd_block, sizeof(int));
+    return key;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -669,7 +727,9 @@ pm_status pm_step_staged(pm_ctx *ctx, const pm_field *field, const pm_decomp *de
         return s;
     if (field->stagger)
         return arg_error("per-stage migration takes a collocated field");
-    pm::DPool dmid{}, dms{};
+    pm::DPool dmid, dms;
+    std::memset(&dmid, 0, sizeof dmid);  // the bytes are part of a graph key
+    std::memset(&dms, 0, sizeof dms);
     s = conv_stage(mid, "mid", dmid);
     if (!s)
         s = conv_stage(mid_send, "mid_send", dms);
@@ -687,16 +747,20 @@ pm_status pm_step_staged(pm_ctx *ctx, const pm_field *field, const pm_decomp *de
                          sh.wg, sh.items);
     ctx->last_shape = sh;
     hipStream_t st = (hipStream_t)stream;
-    const bool timed = ctx->tmax > 0 && ctx->tcount + 1 < ctx->tmax;
-    pm::KArgs k1 = k;  // stage 1: in -> mid, leavers through mid_send
-    k1.out = dmid;
-    k1.send = dms;
-    s = queue_stage(ctx, k1, mixed, 1, sh, st, timed);
-    if (s)
-        return s;
-    pm::KArgs k2 = k;  // stage 2: mid -> out, leavers through send
-    k2.in = dmid;
-    return queue_stage(ctx, k2, mixed, 2, sh, st, timed);
+    pm::KArgs ks[2] = {k, k};
+    ks[0].out = dmid;  // stage 1: in -> mid, leavers through mid_send
+    ks[0].send = dms;
+    ks[1].in = dmid;   // stage 2: mid -> out, leavers through send
+    auto queue = [&](hipStream_t qs, bool timed) {
+        pm::KArgs k1 = ks[0], k2 = ks[1];
+        pm_status r = queue_stage(ctx, k1, mixed, 1, sh, qs, timed);
+        return r ? r : queue_stage(ctx, k2, mixed, 2, sh, qs, timed);
+    };
+    if (!ctx->use_graph)
+        return queue(st, ctx->tmax > 0 && ctx->tcount + 1 < ctx->tmax);
+    // graph path: one captured graph (both stages) per argument set and shape
+    return run_captured(ctx, graph_key(ctx, 'S', ks, 2, sh), st,
+                        [&](hipStream_t cs) { return queue(cs, false); });
 }
 
 pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
@@ -717,39 +781,10 @@ pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
     const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
     k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(k.sub_count);
-    std::vector<unsigned char> key(sizeof k + sizeof sh + 2 * sizeof(int));
-    std::memcpy(key.data(), &k, sizeof k);
-    std::memcpy(key.data() + sizeof k, &sh, sizeof sh);
-    std::memcpy(key.data() + sizeof k + sizeof sh, &ctx->blocks_per_cu, sizeof(int));
-    std::memcpy(key.data() + sizeof k + sizeof sh + sizeof(int), &ctx->xcd_block, sizeof(int));
-    for (auto &g : ctx->graphs)
-        if (g.key == key) {
-            PM_HIP(hipGraphLaunch(g.exec, st), "graph launch");
-            return PM_OK;
-        }
-    if (!ctx->cap_stream)
-        PM_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "stream create");
-    PM_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal),
-           "begin capture");
-    pm_status qs = queue_step(ctx, k, mixed, ctx->cap_stream, false);
-    hipGraph_t graph = nullptr;
-    hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &graph);
-    if (qs)
-        return qs;
-    if (ce != hipSuccess)
-        return hip_error(ce, "end capture");
-    hipGraphExec_t exec = nullptr;
-    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess)
-        return hip_error(ie, "graph instantiate");
-    if (ctx->graphs.size() >= 16) {
-        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
-        ctx->graphs.erase(ctx->graphs.begin());
-    }
-    ctx->graphs.push_back({key, exec});
-    PM_HIP(hipGraphLaunch(exec, st), "graph launch");
-    return PM_OK;
+    return run_captured(ctx, graph_key(ctx, 'P', &k, 1, sh), st, [&](hipStream_t cs) {
+        pm::KArgs kk = k;
+        return queue_step(ctx, kk, mixed, cs, false);
+    });
 }
 
 pm_status pm_get_status(pm_ctx *ctx, void *stream, uint32_t *flags)

@@ -294,31 +294,35 @@ def test_repeated_steps_are_deterministic():
 
 
 def test_graph_replays_match_eager():
+    """Every replay (two graphs, one per ping-pong direction, three replays
+    each, with eager torch work and synchronisations in between) against the
+    eager step it stands for, bit for bit."""
     say("[test] graph replays")
     c = Case("C1")
     pa, send = c.pin(), c.send()
     pb = c.pout(pa.size)
     ctx = c.ctx(pa, send)
-    # eager reference: 6 steps ping-pong
     ea, eb = c.pin(), c.pout(pa.size)
+    ref = []
     for _ in range(6):
         ctx.step(c.field, c.dc, ea, eb, send, c.params)
         ea, eb = eb, ea
-    ref = ea.to_host()
+        ref.append(ea.to_host())
     ctx.set_graph(True)
     for k in range(6):
         ctx.step(c.field, c.dc, pa, pb, send, c.params)
         pa, pb = pb, pa
         torch.cuda.synchronize()
         _ = pa.x.sum().item()  # eager torch work between replays
+        got = pa.to_host()
+        np.testing.assert_array_equal(got.count, ref[k].count, err_msg=f"replay {k}")
+        for q in range(c.dc.nsub):
+            s = seg(ref[k], q)
+            np.testing.assert_array_equal(got.x[:, s], ref[k].x[:, s], err_msg=f"replay {k}")
+            np.testing.assert_array_equal(got.v[:, s], ref[k].v[:, s], err_msg=f"replay {k}")
+            np.testing.assert_array_equal(got.id[s], ref[k].id[s], err_msg=f"replay {k}")
     ctx.set_graph(False)
     assert ctx.get_status() == 0
-    got = pa.to_host()
-    np.testing.assert_array_equal(got.count, ref.count)
-    for q in range(c.dc.nsub):
-        s = seg(ref, q)
-        np.testing.assert_array_equal(got.x[:, s], ref.x[:, s])
-        np.testing.assert_array_equal(got.id[s], ref.id[s])
 
 
 # ---------------------------------------------------------------------------

@@ -91,3 +91,39 @@ def test_unbuilt_shape_and_mac_field_are_argument_errors():
                          stagger=True)
     with pytest.raises(pm.PMError, match="collocated"):
         ctx.step_staged(mac, c.dc, pin, mid, msend, pout, send, c.params)
+
+
+def test_staged_graph_replays_match_eager():
+    """pm_step_staged under pm_set_graph: every replay (two graphs, three
+    replays each, eager torch work in between) equals the eager step."""
+    say("[test] staged graph replays")
+    c = Case("C2S", 40000, 32, (4, 4, 4), face=0.2, edge=0.05, corner=0.03)
+    c.params.dt = min(c.dt, 0.015)
+    pa, send = c.pin(), c.send()
+    pb = c.pout(pa.size)
+    mid = pm.DeviceStagePool.empty(c.host.base, c.host.cap, device=c.dev, size=pa.size)
+    msend = pm.DeviceStagePool.empty(c.sb, c.sc, device=c.dev, size=send.size)
+    ctx = c.ctx(pa, send)
+    ea, eb = c.pin(), c.pout(pa.size)
+    ref = []
+    for _ in range(6):
+        ctx.step_staged(c.field, c.dc, ea, mid, msend, eb, send, c.params)
+        ea, eb = eb, ea
+        ref.append(ea.to_host())
+    assert ctx.get_status() == 0
+    ctx.set_graph(True)
+    for k in range(6):
+        ctx.step_staged(c.field, c.dc, pa, mid, msend, pb, send, c.params)
+        pa, pb = pb, pa
+        torch.cuda.synchronize()
+        _ = pa.x.sum().item()  # eager torch work between replays
+        got = pa.to_host()
+        np.testing.assert_array_equal(got.count, ref[k].count, err_msg=f"replay {k}")
+        for q in range(c.dc.nsub):
+            b, n = int(ref[k].base[q]), int(ref[k].count[q])
+            for name in ("x", "v", "tau", "id"):
+                np.testing.assert_array_equal(getattr(got, name)[..., b:b + n],
+                                              getattr(ref[k], name)[..., b:b + n],
+                                              err_msg=f"replay {k} {name} seg {q}")
+    ctx.set_graph(False)
+    assert ctx.get_status() == 0
