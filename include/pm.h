@@ -207,8 +207,10 @@ typedef struct {
 /* Launch shape of the tile kernels: workgroup size (256 or 512), records
  * per thread (1, 2, 4 or 8); tile = wg*items records.  wg = 0 in
  * pm_set_tuning selects the per-variant defaults (256 x 4; 256 x 2 for FP64
- * periodic fields with the nonlinear drag law or the MAC arrangement), which
- * a context uses until
+ * periodic fields with the nonlinear drag law or the MAC arrangement and for
+ * per-stage migration; records per thread halved while the context's pool
+ * extent gives fewer than two tiles per compute unit), which a context uses
+ * until
  * pm_set_tuning or pm_autotune fixes a shape; pm_get_tuning then reports the
  * shape of the last launch.  blocks_per_cu is the persistent grid's
  * workgroups per compute unit: 0 = the runtime's occupancy estimate; an
@@ -334,7 +336,8 @@ pm_status pm_kernel_times(pm_ctx *ctx, int32_t *n, double *total_ms, float *ms,
  * `send`).  Each exchange is the same scan, pack, compact and append as
  * pm_step's.  Collocated fields only; `in` is unchanged; mid must fit the
  * context's pool extent and mid_send its send extent.  Launch shapes with
- * at most 1024 records per tile (default 256 x 2).  Replayed as one HIP
+ * at most 1024 records per tile (default 256 x 2, or fewer records per
+ * thread for small pools as in pm_tuning).  Replayed as one HIP
  * graph of both stages under pm_set_graph, like pm_step; eager launches
  * record both stages' fused kernels under pm_set_timing. */
 pm_status pm_step_staged(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,

@@ -288,16 +288,27 @@ pm_status check_range(pm_ctx *ctx, int32_t nsub, int32_t first, int32_t count)
     return PM_OK;
 }
 
+// Records per thread of the default shape: at most max_items, halved while
+// the context's pool extent would give fewer than two tiles per compute unit
+// (a pool of 65,536 particles steps in 0.045 ms at 256 x 1 against 0.059 ms
+// at 256 x 4: its 64 large tiles leave most of the chip idle).
+int auto_items(const pm_ctx *ctx, int max_items)
+{
+    int items = max_items;
+    while (items > 1 && ctx->ws.pool_extent / (256 * (int64_t)items) < 2 * (int64_t)ctx->cus)
+        items /= 2;
+    return items;
+}
+
 // Launch shape of a call: the tuned one, else a measured default — 256
 // threads x 4 records, except the FP64 periodic kernels with the nonlinear
 // drag law or a MAC field, whose 4-record variants run out of registers
-// (x 2 records).
+// (x 2 records); fewer records per thread for small pools (auto_items).
 pm::Shape shape_for(pm_ctx *ctx, bool mixed, bool halo, bool nonlinear, bool stagger)
 {
     pm::Shape sh = ctx->shape;
     if (ctx->shape_auto)
-        sh = (!mixed && !halo && (nonlinear || stagger)) ? pm::Shape{256, 2}
-                                                         : pm::Shape{256, 4};
+        sh = pm::Shape{256, auto_items(ctx, (!mixed && !halo && (nonlinear || stagger)) ? 2 : 4)};
     ctx->last_shape = sh;
     return sh;
 }
@@ -741,7 +752,7 @@ pm_status pm_step_staged(pm_ctx *ctx, const pm_field *field, const pm_decomp *de
         return arg_error("mid.nsub must equal in.nsub");
     if (mid->x[0] == in->x[0] || mid->x[0] == out->x[0])
         return arg_error("mid must differ from in and out");
-    const pm::Shape sh = ctx->shape_auto ? pm::Shape{256, 2} : ctx->shape;
+    const pm::Shape sh = ctx->shape_auto ? pm::Shape{256, auto_items(ctx, 2)} : ctx->shape;
     if (!pm::stage_shape_supported(sh))
         return arg_error("launch shape wg=%d items=%d is not built for per-stage migration",
                          sh.wg, sh.items);

@@ -93,21 +93,36 @@ def test_bad_drag_parameters_are_argument_errors():
 
 
 def test_default_launch_shape_follows_the_variant():
+    """256 x 4 by default, 256 x 2 for the FP64 periodic nonlinear-drag (and
+    MAC) kernels, whose 4-record variants run out of registers; fewer
+    records per thread when the context's pool extent gives fewer than two
+    tiles per compute unit."""
     from paper_2604_11008_amd import pm
     say("[test] per-variant default shapes")
     c = Case("C3", 50000, 32, (4, 4, 4), drag="nonlinear")
-    pin, send = c.pin(), c.send()
-    pout = c.pout(pin.size)
-    ctx = c.ctx(pin, send)
+    send = c.send()
     stokes = pm.Params(c.dt, c.g)
-    ctx.step(c.field, c.dc, pin, pout, send, c.params)
-    assert ctx.get_tuning()[:2] == (256, 2)
-    ctx.step(c.field, c.dc, pin, pout, send, stokes)
-    assert ctx.get_tuning()[:2] == (256, 4)
-    ctx.set_tuning(256, 1)
-    ctx.step(c.field, c.dc, pin, pout, send, c.params)
-    assert ctx.get_tuning()[:2] == (256, 1)
-    ctx.set_tuning(0, 0)
-    ctx.step(c.field, c.dc, pin, pout, send, c.params)
-    assert ctx.get_tuning()[:2] == (256, 2)
-    assert ctx.get_status() == 0
+    # the same particles in pools padded to a large extent
+    extent = 1 << 22
+    pin = pm.DevicePool.from_host(c.host, c.dev, size=extent)
+    pout = c.pout(extent)
+    big = pm.Context(extent, send.size, c.dc.nsub, device=c.dev)
+    big.step(c.field, c.dc, pin, pout, send, c.params)
+    assert big.get_tuning()[:2] == (256, 2)
+    big.step(c.field, c.dc, pin, pout, send, stokes)
+    assert big.get_tuning()[:2] == (256, 4)
+    big.set_tuning(256, 1)
+    big.step(c.field, c.dc, pin, pout, send, c.params)
+    assert big.get_tuning()[:2] == (256, 1)
+    big.set_tuning(0, 0)
+    big.step(c.field, c.dc, pin, pout, send, c.params)
+    assert big.get_tuning()[:2] == (256, 2)
+    assert big.get_status() == 0
+    # the unpadded pool (about 1.2e5 records) gives fewer than two
+    # 256-record tiles per CU
+    spin = c.pin()
+    spout = c.pout(spin.size)
+    small = c.ctx(spin, send)
+    small.step(c.field, c.dc, spin, spout, send, stokes)
+    assert small.get_tuning()[:2] == (256, 1)
+    assert small.get_status() == 0

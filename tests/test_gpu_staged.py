@@ -38,7 +38,8 @@ def test_staged_step_matches_oracle(name, npart, n, p, drag):
     ctx = c.ctx(pin, send)
     ctx.step_staged(c.field, c.dc, pin, mid, msend, pout, send, c.params)
     flags = ctx.get_status()
-    assert ctx.get_tuning()[:2] == (256, 2)
+    wg, items = ctx.get_tuning()[:2]
+    assert wg == 256 and items <= 2  # the per-stage default, fewer for small pools
     rmid = gen.empty_stage_pool(c.host.base, c.host.cap)
     rms = gen.empty_stage_pool(c.sb, c.sc)
     rout, rsend = gen.empty_pool(c.host.base, c.host.cap), gen.empty_pool(c.sb, c.sc)
