@@ -134,6 +134,14 @@ def _p(t: torch.Tensor):
     return t.data_ptr()
 
 
+def _rows(t: torch.Tensor):
+    """Pointers of the three rows of a contiguous (3, n) tensor (computed, so
+    that no row views are made on every call)."""
+    p = t.data_ptr()
+    step = t.stride(0) * t.element_size()
+    return (C.c_void_p * 3)(p, p + step, p + 2 * step)
+
+
 # --- device-side objects -------------------------------------------------------------
 
 class DeviceField:
@@ -251,15 +259,11 @@ class DevicePool:
 
     def particles(self):
         return _Particles(self.nseg, self.vdtype, _p(self.base), _p(self.cap), _p(self.count),
-                          (C.c_void_p * 3)(*[_p(self.x[a]) for a in range(3)]),
-                          (C.c_void_p * 3)(*[_p(self.v[a]) for a in range(3)]),
-                          _p(self.tau), _p(self.id))
+                          _rows(self.x), _rows(self.v), _p(self.tau), _p(self.id))
 
     def sendbufs(self):
         return _Send(_p(self.base), _p(self.cap), _p(self.count),
-                     (C.c_void_p * 3)(*[_p(self.x[a]) for a in range(3)]),
-                     (C.c_void_p * 3)(*[_p(self.v[a]) for a in range(3)]),
-                     _p(self.tau), _p(self.id))
+                     _rows(self.x), _rows(self.v), _p(self.tau), _p(self.id))
 
     def extent(self):
         return int((self.base + self.cap).max().item()) if self.nseg else 0
@@ -272,8 +276,8 @@ class DeviceStagePool(DevicePool):
     def __init__(self, x, v, xs, vs, a, tau, ids, base, cap, count):
         super().__init__(x, v, tau, ids, base, cap, count)
         self.xs, self.vs, self.a = xs, vs, a
-        if xs.shape != x.shape or xs.dtype != torch.float64:
-            raise PMError("xs must be a float64 (3, size) tensor")
+        if xs.shape != x.shape or xs.dtype != torch.float64 or not xs.is_contiguous():
+            raise PMError("xs must be a contiguous float64 (3, size) tensor")
         for t in (vs, a):
             if t.shape != v.shape or t.dtype != v.dtype or not t.is_contiguous():
                 raise PMError("vs and a must match v")
@@ -290,7 +294,7 @@ class DeviceStagePool(DevicePool):
         return h
 
     def _arr(self, t):
-        return (C.c_void_p * 3)(*[_p(t[k]) for k in range(3)])
+        return _rows(t)
 
     def stage_particles(self):
         return _StageParticles(self.nseg, self.vdtype, _p(self.base), _p(self.cap),

@@ -86,3 +86,27 @@ def test_host_only_calls():
     assert lib.pm_create(ctypes.byref(h), None, 0, 100, 100, 0) == 1
     assert b"nsub" in lib.pm_last_error()
     assert lib.pm_create(None, None, 0, 100, 100, 1) == 1
+
+
+def test_binding_passes_the_row_pointers_of_each_array():
+    """The structs handed to the library carry, for every (3, n) array, the
+    addresses of its three rows (host tensors stand in for device ones)."""
+    import numpy as np
+    import torch
+    from paper_2604_11008_amd import gen, pm
+    base = np.array([0, 40, 90], dtype=np.int64)
+    cap = np.array([40, 50, 30], dtype=np.int64)
+    for vdt in (torch.float64, torch.float32):
+        p = pm.DevicePool.empty(base, cap, vdtype=vdt, device="cpu", size=130)
+        pc, sc = p.particles(), p.sendbufs()
+        for name in ("x", "v"):
+            want = [getattr(p, name)[a].data_ptr() for a in range(3)]
+            assert [getattr(pc, name)[a] for a in range(3)] == want
+            assert [getattr(sc, name)[a] for a in range(3)] == want
+        st = pm.DeviceStagePool.empty(base, cap, vdtype=vdt, device="cpu", size=130)
+        spc, ssc = st.stage_particles(), st.stage_sendbufs()
+        for name in ("x", "v", "xs", "vs", "a"):
+            want = [getattr(st, name)[a].data_ptr() for a in range(3)]
+            assert [getattr(spc, name)[a] for a in range(3)] == want
+            assert [getattr(ssc, name)[a] for a in range(3)] == want
+    assert gen is not None
