@@ -167,3 +167,39 @@ def test_staged_mixed_precision_matches_the_per_step_path():
     dx = np.minimum(dx, np.abs(dx - c.wl.L))
     say(f"  stage-1 migrants {int(msend.count.sum().item())}; max |dx| {dx.max():.2e}")
     assert dx.max() <= 8 * np.spacing(c.wl.L)
+
+
+def test_stage_one_overflow_counts_exactly_and_a_retry_succeeds():
+    """mid_send buffers of one record: the stage-1 exchange flags
+    SEND_OVERFLOW and still counts every leaver exactly (as the oracle
+    does); `in` is intact, so a retry with regrown buffers gives the oracle's
+    state."""
+    say("[test] staged stage-1 overflow")
+    c = Case("C2S", 40000, 32, (4, 4, 4), face=0.2, edge=0.05, corner=0.03)
+    c.params.dt = min(c.dt, 0.015)
+    pin, send = c.pin(), c.send()
+    pout = c.pout(pin.size)
+    small = np.minimum(c.sc, 1)
+    mid = pm.DeviceStagePool.empty(c.host.base, c.host.cap, device=c.dev, size=pin.size)
+    msend = pm.DeviceStagePool.empty(c.sb, small, device=c.dev, size=send.size)
+    ctx = c.ctx(pin, send)
+    ctx.step_staged(c.field, c.dc, pin, mid, msend, pout, send, c.params)
+    flags = ctx.get_status()
+    say(f"  flags {pm.flag_names(flags)}")
+    assert flags & pm.SEND_OVERFLOW
+    rmid = gen.empty_stage_pool(c.host.base, c.host.cap)
+    rms = gen.empty_stage_pool(c.sb, c.sc)
+    rout, rsend = gen.empty_pool(c.host.base, c.host.cap), gen.empty_pool(c.sb, c.sc)
+    oflags = oracle.step_staged(c.ofield, c.odc, c.params.dt, c.g, c.host, rmid, rms, rout,
+                                rsend)
+    assert oflags == 0
+    np.testing.assert_array_equal(msend.to_host().count, rms.count)
+    assert np.any(rms.count > small)  # some buffer held more than its one slot
+    # regrow and retry from the intact input
+    msend2 = pm.DeviceStagePool.empty(c.sb, c.sc, device=c.dev, size=send.size)
+    send2 = c.send()
+    ctx.step_staged(c.field, c.dc, pin, mid, msend2, pout, send2, c.params)
+    assert ctx.get_status() == 0
+    delta = c.wl.L / c.wl.n
+    compare_mid(msend2.to_host(), rms, c.dc.nsub * 27, c.wl.L, delta, "mid_send")
+    compare_pools(pout.to_host(), rout, c.dc.nsub, c.wl.L, delta, what="out")
