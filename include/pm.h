@@ -358,6 +358,23 @@ pm_status pm_touched_nodes(pm_ctx *ctx, const pm_field *field,
                            int64_t *touched);
 
 /* Text of the last host-side error of this thread. */
+/* Cell re-sort of every segment of `in` into `out` (same nsub; out's
+ * segments must hold in's counts): each segment's records ordered by the
+ * cell they lie in -- cell (i,j,k) = floor(x_a n_a / L_a) clamped to
+ * [0, n_a-1], keyed by the Z-order code of (i/2, j, k) times two plus the
+ * parity of i -- and, within a cell, by their position in `in`.  Counts are
+ * copied.  Not a step of the paper's method, which never reorders
+ * particles: the fused step's stencil gathers share cache lines when
+ * neighbouring records are neighbours in space, and particles disperse from
+ * any order as they move, so a caller re-sorts every few tens of steps.
+ * workspace: caller-owned device memory of at least
+ * pm_sort_workspace_bytes(pool_extent, nsub) bytes for the context's pool
+ * extent (below 2^32), 256-byte aligned.  Asynchronous; in is unchanged;
+ * a segment of out too small for its count sets PM_F_DEST_OVERFLOW. */
+size_t pm_sort_workspace_bytes(int64_t pool_extent, int32_t nsub);
+pm_status pm_sort(pm_ctx *ctx, const pm_field *field, const pm_particles *in,
+                  pm_particles *out, void *workspace, size_t ws_bytes, void *stream);
+
 const char *pm_last_error(void);
 
 #ifdef __cplusplus

@@ -1024,6 +1024,99 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
     return PM_OK;
 }
 
+// Layout of the re-sort workspace.
+struct SortLayout {
+    size_t keys[2], vals[2], hist, off, total;
+    int64_t tiles;
+};
+
+static SortLayout sort_layout(int64_t pool_extent, int32_t nsub)
+{
+    SortLayout L{};
+    const size_t pe = (size_t)std::max<int64_t>(pool_extent, 1);
+    const size_t tiles = (size_t)(pool_extent / pm::sort_tile()) + (size_t)nsub + 1;
+    L.tiles = (int64_t)tiles;
+    size_t o = 0;
+    for (int b = 0; b < 2; ++b) {
+        L.keys[b] = o;
+        o += align256(pe * sizeof(uint64_t));
+    }
+    for (int b = 0; b < 2; ++b) {
+        L.vals[b] = o;
+        o += align256(pe * sizeof(uint32_t));
+    }
+    L.hist = o;
+    o += align256(tiles * 256 * sizeof(uint32_t));
+    L.off = o;
+    o += align256(tiles * 256 * sizeof(int64_t));
+    L.total = o;
+    return L;
+}
+
+size_t pm_sort_workspace_bytes(int64_t pool_extent, int32_t nsub)
+{
+    if (pool_extent < 0 || pool_extent >= ((int64_t)1 << 32) || nsub < 1 || nsub > PM_MAX_NSUB)
+        return 0;
+    return sort_layout(pool_extent, nsub).total;
+}
+
+pm_status pm_sort(pm_ctx *ctx, const pm_field *field, const pm_particles *in,
+                  pm_particles *out, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!ctx)
+        return arg_error("ctx is NULL");
+    pm::KArgs k;
+    base_args(ctx, k);
+    bool mixed = false;
+    pm_status s = conv_field(field, k.f, mixed);
+    if (!s)
+        s = conv_pool(in, "in", mixed, k.in);
+    if (!s)
+        s = conv_pool(out, "out", mixed, k.out);
+    if (!s)
+        s = check_range(ctx, in->nsub, 0, in->nsub);
+    if (s)
+        return s;
+    if (out->nsub != in->nsub)
+        return arg_error("out.nsub must equal in.nsub");
+    if (in->x[0] == out->x[0])
+        return arg_error("in and out must be different pools");
+    if (ctx->ws.pool_extent >= ((int64_t)1 << 32))
+        return arg_error("the re-sort takes pool extents below 2^32");
+    const SortLayout L = sort_layout(ctx->ws.pool_extent, in->nsub);
+    if (!workspace || ws_bytes < L.total)
+        return arg_error("sort workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                         L.total);
+    if (((uintptr_t)workspace & 255u) != 0)
+        return arg_error("sort workspace must be 256-byte aligned");
+    char *w = (char *)workspace;
+    pm::DSort d;
+    for (int b = 0; b < 2; ++b) {
+        d.keys[b] = (uint64_t *)(w + L.keys[b]);
+        d.vals[b] = (uint32_t *)(w + L.vals[b]);
+    }
+    d.hist = (uint32_t *)(w + L.hist);
+    d.off = (int64_t *)(w + L.off);
+    d.tiles = L.tiles;
+    // radix passes over the key's bits: 3 bits per Z-order level plus the
+    // parity bit of x
+    int m = std::max({(field->n[0] - 1) >> 1, field->n[1] - 1, field->n[2] - 1, 1});
+    int bits = 0;
+    while (m) {
+        ++bits;
+        m >>= 1;
+    }
+    const int passes = (3 * bits + 1 + 7) / 8;
+    k.sub_first = 0;
+    k.sub_count = in->nsub;
+    k.tile = pm::sort_tile();
+    hipStream_t st = (hipStream_t)stream;
+    PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn | pm::kPrepCheckOut, st),
+           "prep launch");
+    PM_HIP(pm::launch_sort(k, d, passes, mixed, std::max(1, ctx->cus * 4), st), "sort launch");
+    return PM_OK;
+}
+
 pm_status pm_touched_nodes(pm_ctx *ctx, const pm_field *field, const pm_particles *in,
                            const pm_params *params, uint64_t *bitmap, int64_t nbits,
                            void *stream, int64_t *touched)

@@ -99,6 +99,17 @@ struct KArgs {
     int32_t cpt;         // append: workgroups per destination
 };
 
+// Work arrays of the cell re-sort (a caller-owned workspace of its own):
+// (key, pool position) pairs in two buffers ping-ponged by the radix passes,
+// and per tile the digit counts and the pool positions they start at.
+struct DSort {
+    uint64_t *keys[2];   // [pool_extent]
+    uint32_t *vals[2];   // [pool_extent]
+    uint32_t *hist;      // [tiles * 256]
+    int64_t *off;        // [tiles * 256]
+    int64_t tiles;       // capacity of hist and off, in tiles
+};
+
 // Prep kernel modes.
 enum {
     kPrepTiles = 1,       // tile_start/ticket for the segment range
@@ -117,6 +128,11 @@ struct Shape {
 
 // Launchers (pm_kernels.hip).  `mixed` selects float32 field/velocities.
 hipError_t launch_prep(const KArgs &a, int mode, hipStream_t st);
+// Cell re-sort (pm_sort.hip): records per tile, and the launches of one sort
+// (keys, `passes` radix passes of 8 bits, gather).
+int sort_tile();
+hipError_t launch_sort(const KArgs &a, DSort s, int passes, bool mixed, int grid,
+                       hipStream_t st);
 hipError_t launch_step(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);
 hipError_t launch_advance(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);
 hipError_t launch_classify(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st);

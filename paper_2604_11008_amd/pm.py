@@ -109,6 +109,8 @@ def lib():
             "pm_kernel_times": ([vp, vp, vp, vp, i32], C.c_int),
             "pm_touched_nodes": ([vp, vp, vp, vp, vp, i64, vp, vp], C.c_int),
             "pm_last_error": ([], C.c_char_p),
+            "pm_sort_workspace_bytes": ([i64, i32], C.c_size_t),
+            "pm_sort": ([vp, vp, vp, vp, vp, C.c_size_t, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -461,6 +463,21 @@ class Context:
         ms = (C.c_float * max_ms)()
         _check(lib().pm_kernel_times(self.h, C.byref(n), C.byref(tot), ms, max_ms))
         return tot.value, list(ms[:min(n.value, max_ms)])
+
+    def sort(self, field, pin, pout, stream=None):
+        """Cell re-sort of every segment of pin into pout (pm_sort); the
+        sort's workspace is allocated on first use and kept."""
+        pc = self._pool(pin, "in")
+        oc = self._pool(pout, "out")
+        nb = int(lib().pm_sort_workspace_bytes(self.pool_extent, pin.nseg))
+        if nb == 0:
+            raise PMError("no re-sort for this pool extent")
+        ws = getattr(self, "sort_workspace", None)
+        if ws is None or ws.numel() < nb:
+            ws = torch.empty(nb, dtype=torch.uint8, device=pin.x.device)
+            self.sort_workspace = ws
+        _check(lib().pm_sort(self.h, C.byref(field.c), C.byref(pc), C.byref(oc), _p(ws),
+                             ws.numel(), _stream(stream)))
 
     def touched_nodes(self, field, pin, params, stream=None):
         pc = self._pool(pin, "in")
