@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--tune", default=None, help="wg,items[,blocks_per_cu[,xcd_block]] or 'auto'")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--resort", type=int, default=0,
+                    help="re-sort the pool by cell (pm_sort) every K steps inside the "
+                         "timed region (0: never, the paper's method)")
     ap.add_argument("--accuracy", action="store_true",
                     help="also run --accuracy-steps untimed steps from the start state and "
                          "report the error of the particles with the lowest ids against "
@@ -393,9 +396,12 @@ def main():
         ctx.set_timing(args.steps * (2 if args.staged else 1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         do_step(pa, pb)
         pa, pb = pb, pa
+        if args.resort and (k + 1) % args.resort == 0:
+            ctx.sort(field, pa, pb)
+            pa, pb = pb, pa
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     f = ctx.get_status()
@@ -472,7 +478,17 @@ def main():
             "compact_append": round(e[1].elapsed_time(e[2]) / reps, 4),
             "migrants": int(sendm.count.sum().item())}
         del sendm, outm, work
-    if not args.graph:
+    if args.resort:
+        # the re-sort alone, on the final state
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ctx.sort(field, pa, pb)
+        e0.record()
+        for _ in range(5):
+            ctx.sort(field, pa, pb)
+        e1.record()
+        torch.cuda.synchronize()
+        extra["sort_ms"] = round(e0.elapsed_time(e1) / 5, 4)
+    if not args.graph and not args.resort:
         # the same steps replayed from captured HIP graphs (two graphs: A->B, B->A)
         ctx.set_timing(0)
         ctx.set_graph(True)
@@ -574,7 +590,8 @@ def main():
                    (f" (run at {args.precision})" if args.precision != "auto" else "") +
                    (", nonlinear drag" if args.drag == "nonlinear" else "") +
                    (", MAC-staggered field" if args.stagger else "") +
-                   (f", {args.order} particle order" if args.order != "canonical" else ""),
+                   (f", {args.order} particle order" if args.order != "canonical" else "") +
+                   (f", re-sorted by cell every {args.resort} steps" if args.resort else ""),
                    "particles": npart, "grid": wl.n, "halo": wl.halo,
                    "subdomains": list(wl.p), "graph": bool(args.graph),
                    "tuning": list(ctx.get_tuning())},
