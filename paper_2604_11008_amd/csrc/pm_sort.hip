@@ -18,19 +18,27 @@ namespace {
 constexpr int kSortWG = 256;
 constexpr int kSortItems = 32;
 constexpr int kSortTile = kSortWG * kSortItems;
+constexpr int kScanBatch = 32;  // tiles whose counts a scan thread loads at once
+
+// The 21 low bits of v moved to bits 0, 3, 6, ..., 60 (the magic-mask bit
+// spreading of Morton encoding: five shift-or-mask steps).
+__device__ __forceinline__ uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0x1fffffu;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
 
 // Z-order code of (i >> 1, j, k) (bit b of each at 3b, 3b+1, 3b+2), times
 // two, plus the parity of i.
 __device__ __forceinline__ uint64_t cell_key(int i, int j, int k)
 {
-    const uint32_t a = (uint32_t)i >> 1, b = (uint32_t)j, c = (uint32_t)k;
-    uint64_t code = 0;
-#pragma unroll
-    for (int bit = 0; bit < 21; ++bit) {
-        code |= (uint64_t)((a >> bit) & 1u) << (3 * bit);
-        code |= (uint64_t)((b >> bit) & 1u) << (3 * bit + 1);
-        code |= (uint64_t)((c >> bit) & 1u) << (3 * bit + 2);
-    }
+    const uint64_t code = spread3((uint32_t)i >> 1) | spread3((uint32_t)j) << 1 |
+                          spread3((uint32_t)k) << 2;
     return code * 2 + ((uint32_t)i & 1u);
 }
 
@@ -120,13 +128,13 @@ __global__ __launch_bounds__(256) void k_sort_scan(const KArgs a, DSort s)
         const int64_t t0 = a.ws.tile_start[sl], t1 = a.ws.tile_start[sl + 1];
         int64_t tot = 0;
         int64_t t = t0;
-        for (; t + 8 <= t1; t += 8) {
-            uint32_t c[8];
+        for (; t + kScanBatch <= t1; t += kScanBatch) {
+            uint32_t c[kScanBatch];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < kScanBatch; ++u)
                 c[u] = s.hist[(t + u) * 256 + d];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < kScanBatch; ++u)
                 tot += c[u];
         }
         for (; t < t1; ++t)
@@ -135,13 +143,13 @@ __global__ __launch_bounds__(256) void k_sort_scan(const KArgs a, DSort s)
         int64_t run = block_scan256(tot, wsum, &all);  // exclusive over digits
         run += a.in.base[a.sub_first + sl];
         t = t0;
-        for (; t + 8 <= t1; t += 8) {
-            uint32_t c[8];
+        for (; t + kScanBatch <= t1; t += kScanBatch) {
+            uint32_t c[kScanBatch];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < kScanBatch; ++u)
                 c[u] = s.hist[(t + u) * 256 + d];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < kScanBatch; ++u) {
                 s.off[(t + u) * 256 + d] = run;
                 run += c[u];
             }
