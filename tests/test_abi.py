@@ -79,8 +79,16 @@ def test_binding_struct_layout_matches_header(tmp_path):
 def test_host_only_calls():
     from paper_2604_11008_amd import pm
     lib = pm.lib()
-    assert lib.pm_workspace_bytes(1 << 20, 1 << 16, 8) > (1 << 20) * 4 + (1 << 16) * 65
+    # a stayer slot per pool record and a 137-byte staging slot per send slot
+    assert lib.pm_workspace_bytes(1 << 20, 1 << 16, 8) > (1 << 20) * 4 + (1 << 16) * 137
     assert lib.pm_workspace_bytes(-1, 0, 8) == 0
+    # the re-sort: two (8-byte key, 4-byte position) buffers per pool record
+    assert lib.pm_sort_workspace_bytes(1 << 20, 8) > (1 << 20) * 24
+    assert lib.pm_sort_workspace_bytes(1 << 32, 8) == 0
+    assert lib.pm_sort_workspace_bytes(-1, 8) == 0
+    assert lib.pm_sort_workspace_bytes(100, 0) == 0
+    assert lib.pm_sort(None, None, None, None, None, 0, None) == 1
+    assert b"ctx" in lib.pm_last_error()
     h = ctypes.c_void_p()
     # argument errors are reported without touching a device
     assert lib.pm_create(ctypes.byref(h), None, 0, 100, 100, 0) == 1
