@@ -115,20 +115,27 @@ __global__ __launch_bounds__(kSortWG) void k_sort_hist(const KArgs a, DSort s, i
     }
 }
 
-// Per segment (one workgroup, thread d = digit d): the pool position where
+// Per segment (one workgroup of 1024 threads: digit d = tid mod 256, part =
+// tid / 256 takes a quarter of the segment's tiles): the pool position where
 // each tile's records of digit d go -- the segment's base, plus the records
 // of smaller digits in the segment, plus those of digit d in earlier tiles.
-__global__ __launch_bounds__(256) void k_sort_scan(const KArgs a, DSort s)
+constexpr int kScanParts = 4;
+
+__global__ __launch_bounds__(256 * kScanParts) void k_sort_scan(const KArgs a, DSort s)
 {
-    __shared__ int64_t wsum[4];
+    __shared__ int64_t part_sum[kScanParts][256];
+    __shared__ int64_t wave_tot[4];
     if (sort_tiles(a, s) < 0)
         return;
-    const int d = threadIdx.x;
+    const int tid = threadIdx.x, d = tid & 255, part = tid >> 8;
     for (int sl = blockIdx.x; sl < a.sub_count; sl += gridDim.x) {
         const int64_t t0 = a.ws.tile_start[sl], t1 = a.ws.tile_start[sl + 1];
+        const int64_t len = (t1 - t0 + kScanParts - 1) / kScanParts;
+        const int64_t p0 = t0 + part * len, p1 = p0 + len < t1 ? p0 + len : t1;
+        // this part's count of digit d
         int64_t tot = 0;
-        int64_t t = t0;
-        for (; t + kScanBatch <= t1; t += kScanBatch) {
+        int64_t t = p0;
+        for (; t + kScanBatch <= p1; t += kScanBatch) {
             uint32_t c[kScanBatch];
 #pragma unroll
             for (int u = 0; u < kScanBatch; ++u)
@@ -137,13 +144,37 @@ __global__ __launch_bounds__(256) void k_sort_scan(const KArgs a, DSort s)
             for (int u = 0; u < kScanBatch; ++u)
                 tot += c[u];
         }
-        for (; t < t1; ++t)
+        for (; t < p1; ++t)
             tot += s.hist[t * 256 + d];
-        int64_t all;
-        int64_t run = block_scan256(tot, wsum, &all);  // exclusive over digits
-        run += a.in.base[a.sub_first + sl];
-        t = t0;
-        for (; t + kScanBatch <= t1; t += kScanBatch) {
+        part_sum[part][d] = tot;
+        __syncthreads();
+        // digit totals, scanned over the digits by the first 256 threads
+        int64_t digit_tot = 0;
+#pragma unroll
+        for (int q = 0; q < kScanParts; ++q)
+            digit_tot += part_sum[q][d];
+        int64_t incl = digit_tot;
+        const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int lo = __shfl_up((int)(uint32_t)incl, off, 64);
+            const int hi = __shfl_up((int)(uint32_t)((uint64_t)incl >> 32), off, 64);
+            const int64_t v = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+            if (lane >= off)
+                incl += v;
+        }
+        if (tid < 256 && lane == 63)
+            wave_tot[w] = incl;
+        __syncthreads();
+        // every part of digit d starts after the smaller digits, then after
+        // the earlier parts of digit d
+        int64_t run = a.in.base[a.sub_first + sl] + incl - digit_tot;
+        for (int v = 0; v < (d >> 6); ++v)
+            run += wave_tot[v];
+        for (int q = 0; q < part; ++q)
+            run += part_sum[q][d];
+        t = p0;
+        for (; t + kScanBatch <= p1; t += kScanBatch) {
             uint32_t c[kScanBatch];
 #pragma unroll
             for (int u = 0; u < kScanBatch; ++u)
@@ -154,12 +185,12 @@ __global__ __launch_bounds__(256) void k_sort_scan(const KArgs a, DSort s)
                 run += c[u];
             }
         }
-        for (; t < t1; ++t) {
+        for (; t < p1; ++t) {
             const uint32_t c = s.hist[t * 256 + d];
             s.off[t * 256 + d] = run;
             run += c;
         }
-        __syncthreads();  // wsum is reused by the next segment
+        __syncthreads();  // part_sum and wave_tot are reused by the next segment
     }
 }
 
@@ -291,7 +322,7 @@ hipError_t launch_sort(const KArgs &a, DSort s, int passes, bool mixed, int grid
     for (int p = 0; p < passes; ++p) {
         hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kSortWG), 0, st, a, s, src, 8 * p);
         hipLaunchKernelGGL(k_sort_scan, dim3(std::max(1, std::min(a.sub_count, 4096))),
-                           dim3(256), 0, st, a, s);
+                           dim3(256 * kScanParts), 0, st, a, s);
         hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kSortWG), 0, st, a, s, src,
                            8 * p);
         src ^= 1;
