@@ -238,7 +238,8 @@ typedef struct pm_ctx pm_ctx;
  * plain path, and a staging area of send_extent leaver records (137 bytes
  * each: the 17 eight-byte values of a mid-step record of per-stage
  * migration, of which a per-step leaver uses 8, plus a direction byte).
- * 0 for invalid sizes. */
+ * 0 for invalid sizes (extents outside 0..2^34, nsub outside
+ * 1..PM_MAX_NSUB). */
 size_t pm_workspace_bytes(int64_t pool_extent, int64_t send_extent, int32_t nsub);
 
 /* Create a context on the current device.  workspace: caller-owned device

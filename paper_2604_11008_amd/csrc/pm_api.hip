@@ -438,9 +438,13 @@ extern "C" {
 
 const char *pm_last_error(void) { return g_err.c_str(); }
 
+// Extents a context accepts (records).
+constexpr int64_t kMaxExtent = (int64_t)1 << 34;
+
 size_t pm_workspace_bytes(int64_t pool_extent, int64_t send_extent, int32_t nsub)
 {
-    if (pool_extent < 0 || send_extent < 0 || nsub < 1)
+    if (pool_extent < 0 || pool_extent > kMaxExtent || send_extent < 0 ||
+        send_extent > kMaxExtent || nsub < 1 || nsub > PM_MAX_NSUB)
         return 0;
     return ws_layout(pool_extent, send_extent, nsub).total;
 }
@@ -453,8 +457,9 @@ pm_status pm_create(pm_ctx **out, void *workspace, size_t ws_bytes, int64_t pool
     *out = nullptr;
     if (nsub < 1 || nsub > PM_MAX_NSUB)
         return arg_error("nsub = %d not in 1..%d", nsub, PM_MAX_NSUB);
-    if (pool_extent < 0 || pool_extent > ((int64_t)1 << 34) || send_extent < 0)
-        return arg_error("pool or send extent out of range");
+    if (pool_extent < 0 || pool_extent > kMaxExtent || send_extent < 0 ||
+        send_extent > kMaxExtent)
+        return arg_error("pool or send extent out of range (0..2^34)");
     const WsLayout L = ws_layout(pool_extent, send_extent, nsub);
     if (!workspace || ws_bytes < L.total)
         return arg_error("workspace of %zu bytes is smaller than the %zu needed", ws_bytes,

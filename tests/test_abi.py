@@ -82,6 +82,9 @@ def test_host_only_calls():
     # a stayer slot per pool record and a 137-byte staging slot per send slot
     assert lib.pm_workspace_bytes(1 << 20, 1 << 16, 8) > (1 << 20) * 4 + (1 << 16) * 137
     assert lib.pm_workspace_bytes(-1, 0, 8) == 0
+    assert lib.pm_workspace_bytes(1 << 35, 0, 8) == 0
+    assert lib.pm_workspace_bytes(100, 1 << 35, 8) == 0
+    assert lib.pm_workspace_bytes(100, 100, 4097) == 0
     # the re-sort: two (8-byte key, 4-byte position) buffers per pool record
     assert lib.pm_sort_workspace_bytes(1 << 20, 8) > (1 << 20) * 24
     assert lib.pm_sort_workspace_bytes(1 << 32, 8) == 0
@@ -94,6 +97,8 @@ def test_host_only_calls():
     assert lib.pm_create(ctypes.byref(h), None, 0, 100, 100, 0) == 1
     assert b"nsub" in lib.pm_last_error()
     assert lib.pm_create(None, None, 0, 100, 100, 1) == 1
+    assert lib.pm_create(ctypes.byref(h), None, 0, 1 << 35, 100, 8) == 1
+    assert b"extent" in lib.pm_last_error()
 
 
 def test_binding_passes_the_row_pointers_of_each_array():
