@@ -87,3 +87,25 @@ def test_sorted_pool_steps_like_the_unsorted_one():
         np.testing.assert_array_equal(a.id[lo:lo + k][oa], b.id[lo:lo + k][ob])
         np.testing.assert_array_equal(a.x[:, lo:lo + k][:, oa], b.x[:, lo:lo + k][:, ob])
         np.testing.assert_array_equal(a.v[:, lo:lo + k][:, oa], b.v[:, lo:lo + k][:, ob])
+
+
+def test_sort_errors_and_overflow():
+    """The same pool as input and output is an argument error; an output
+    segment smaller than its count gets PM_F_DEST_OVERFLOW, the exact count,
+    and the records that fit (the first ones in sorted order)."""
+    say("[test] re-sort errors")
+    c = Case("C2S", 60000, 32, (4, 4, 4), order="shuffled")
+    pin, send = c.pin(), c.send()
+    ctx = c.ctx(pin, send)
+    with pytest.raises(pm.PMError, match="different"):
+        ctx.sort(c.field, pin, pin)
+    small_cap = np.maximum(c.host.count - 5, 0)
+    pout = pm.DevicePool.empty(c.host.base, small_cap, device=c.dev, size=pin.size)
+    ctx.sort(c.field, pin, pout)
+    flags = ctx.get_status()
+    assert flags == pm.DEST_OVERFLOW, pm.flag_names(flags)
+    hi, ho = pin.to_host(), pout.to_host()
+    np.testing.assert_array_equal(ho.count, hi.count)
+    for s, src in enumerate(expected(hi, c.wl.n, c.wl.L)):
+        b, k = int(ho.base[s]), int(small_cap[s])
+        np.testing.assert_array_equal(ho.id[b:b + k], hi.id[src[:k]])
