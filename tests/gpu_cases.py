@@ -25,17 +25,20 @@ class Case:
 
     def __init__(self, name, npart=None, n=None, p=None, order="canonical", mode=None,
                  face=0.1, edge=0.03, corner=0.02, dt_scale=1.0, slack=0.05, extra=1024,
-                 drag="stokes", stagger=False):
+                 drag="stokes", stagger=False, field_backend="numpy"):
         say(f"[case] {name} np={npart} n={n} p={p} order={order} mode={mode} drag={drag} "
             f"stagger={stagger}")
         self.drag = drag
         self.wl = gen.make_workload(name, np_override=npart, n_override=n, p_override=p,
-                                    order=order, slack=slack, extra=extra)
+                                    order=order, slack=slack, extra=extra,
+                                    field_backend=field_backend)
         wl = self.wl
         self.mode = mode or wl.mode
         self.dt = wl.dt * dt_scale
         self.g = wl.g
-        self.fh = wl.stored_field(np.float64)
+        # the oracle reads host arrays (a device-generated field is copied back)
+        self.fh = [u if isinstance(u, np.ndarray) else u.cpu().numpy()
+                   for u in wl.stored_field(np.float64)]
         # a MAC case reads the same arrays as staggered components
         self.ofield = oracle.Field(self.fh, wl.n, wl.halo, wl.L, stagger=stagger)
         self.odc = oracle.Decomp(wl.p, wl.bounds)

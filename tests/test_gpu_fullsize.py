@@ -97,3 +97,24 @@ def test_full_size_staged_step_matches_the_oracle(name):
     ex, ev = compare_pools(pout.to_host(), rout, c.dc.nsub, c.wl.L, delta, what="out")
     say(f"  stage-1 migrants {int(rms.count.sum())}, stage-2 {int(rsend.count.sum())}; "
         f"max rel err x {ex:.2e} v {ev:.2e}")
+
+
+def test_full_size_blob_workload_matches_the_oracle():
+    """The 512^3 blob-clustered workload at full size (2^26 particles, 4x4x4
+    subdomains, field synthesised on the device like the benchmark's): one
+    fused step against one whole oracle step."""
+    say("[test] full-size C3")
+    c = Case("C3", face=0.05, edge=0.01, corner=0.005, slack=0.25, extra=4096,
+             field_backend="device")
+    pin, send = c.pin(), c.send()
+    pout = c.pout(pin.size)
+    ctx = c.ctx(pin, send)
+    ctx.step(c.field, c.dc, pin, pout, send, c.params)
+    flags = ctx.get_status()
+    say(f"  gpu flags {flags}, shape {ctx.get_tuning()}")
+    ref_out, ref_send, _, oflags = c.oracle_step()
+    assert flags == oflags == 0
+    delta = c.wl.L / c.wl.n
+    compare_pools(send.to_host(), ref_send, c.dc.nsub * 27, c.wl.L, delta, what="send")
+    ex, ev = compare_pools(pout.to_host(), ref_out, c.dc.nsub, c.wl.L, delta, what="out")
+    say(f"  migrants {int(ref_send.count.sum())}; max rel err x {ex:.2e} v {ev:.2e}")
