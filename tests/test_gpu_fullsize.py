@@ -99,12 +99,14 @@ def test_full_size_staged_step_matches_the_oracle(name):
         f"max rel err x {ex:.2e} v {ev:.2e}")
 
 
-def test_full_size_blob_workload_matches_the_oracle():
-    """The 512^3 blob-clustered workload at full size (2^26 particles, 4x4x4
-    subdomains, field synthesised on the device like the benchmark's): one
-    fused step against one whole oracle step."""
-    say("[test] full-size C3")
-    c = Case("C3", face=0.05, edge=0.01, corner=0.005, slack=0.25, extra=4096,
+@pytest.mark.parametrize("name", ["C3", "C4"])
+def test_full_size_batched_workload_matches_the_oracle(name):
+    """The 512^3 workloads at full size, field synthesised on the device like
+    the benchmark's: blob-clustered 2^26 particles in 4x4x4 subdomains, and
+    lognormal counts (about 8.2e7 particles) in 8x8x8: one fused step against
+    one whole oracle step."""
+    say(f"[test] full-size {name}")
+    c = Case(name, face=0.05, edge=0.01, corner=0.005, slack=0.25, extra=4096,
              field_backend="device")
     pin, send = c.pin(), c.send()
     pout = c.pout(pin.size)
