@@ -79,8 +79,9 @@ typedef enum { PM_F64 = 0, PM_F32 = 1 } pm_dtype;
 #define PM_F_NONFINITE     8u  /* a position coordinate was NaN or +-inf       */
 #define PM_F_HALO          16u /* an interpolation stencil left the stored grid */
 #define PM_F_LAYOUT        32u /* count > cap, a segment beyond the pool extent
-                                  given to pm_create, or more tiles than the
-                                  workspace holds                               */
+                                  given to pm_create, or more tiles than
+                                  non-overlapping segments of that extent give
+                                  (overlapping segments)                        */
 
 /* Limits. */
 #define PM_MAX_P    32     /* subdomains per axis                             */
@@ -282,8 +283,10 @@ pm_status pm_compact_append(pm_ctx *ctx, const pm_decomp *decomp,
                             pm_particles *out, int32_t sub_first,
                             int32_t sub_count, void *stream);
 
-/* The whole step in -> out for all subdomains, fused into one persistent
- * launch plus the on-device exchange; `in` is left unchanged.  Results are
+/* The whole step in -> out for all subdomains: interpolation and the Heun
+ * update (Sect. 2.2), mask, scan and pack (Sect. 2.3.3), compaction and
+ * receive (unpacking, Sect. 3.2.2), fused into one persistent launch plus
+ * the on-device exchange; `in` is left unchanged.  Results are
  * bitwise equal to pm_interp_advance (on a copy of in), then
  * pm_classify_scan_pack, then pm_compact_append, over all subdomains.
  * With graphs enabled (pm_set_graph) the launches are captured once per
@@ -292,7 +295,13 @@ pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
                   const pm_particles *in, pm_particles *out,
                   pm_sendbufs *send, const pm_params *params, void *stream);
 
-/* Synchronise `stream`, return the flag word (PM_F_*) and clear it. */
+/* Synchronise `stream`, return the flag word (PM_F_*) and clear it.
+ * The capacities that would have sufficed after an overflow need no
+ * out-parameter: the counts the step writes are exact whatever the
+ * capacities (out->count[s] for every destination segment, send->count[s*27+d]
+ * for every send buffer; records beyond a capacity are not written), so the
+ * caller reads them from those device arrays, grows the segments and repeats
+ * the step from the unchanged `in`. */
 pm_status pm_get_status(pm_ctx *ctx, void *stream, uint32_t *flags);
 
 pm_status pm_set_tuning(pm_ctx *ctx, const pm_tuning *t);
@@ -358,7 +367,6 @@ pm_status pm_touched_nodes(pm_ctx *ctx, const pm_field *field,
                            uint64_t *bitmap, int64_t nbits, void *stream,
                            int64_t *touched);
 
-/* Text of the last host-side error of this thread. */
 /* Cell re-sort of every segment of `in` into `out` (same nsub; out's
  * segments must hold in's counts): each segment's records ordered by the
  * cell they lie in -- cell (i,j,k) = floor(x_a n_a / L_a) clamped to
@@ -376,6 +384,7 @@ size_t pm_sort_workspace_bytes(int64_t pool_extent, int32_t nsub);
 pm_status pm_sort(pm_ctx *ctx, const pm_field *field, const pm_particles *in,
                   pm_particles *out, void *workspace, size_t ws_bytes, void *stream);
 
+/* Text of the last host-side error of this thread. */
 const char *pm_last_error(void);
 
 #ifdef __cplusplus

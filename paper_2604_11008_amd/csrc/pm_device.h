@@ -765,6 +765,11 @@ __global__ __launch_bounds__(256) void k_prep(const KArgs a, int mode)
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + tid;
     const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
     uint32_t bad = 0;
+    // look-back words cleared below: enough for every tile of non-overlapping
+    // segments within the pool extent (a layout with more tiles is rejected)
+    int64_t lb_words = (int64_t)a.ws.pool_extent / a.tile + a.sub_count + 2;
+    if (lb_words > a.ws.max_tiles)
+        lb_words = a.ws.max_tiles;
 
     if ((mode & (kPrepTiles | kPrepStaging)) && blockIdx.x == 0) {
         __shared__ int64_t segv[PM_MAX_NSUB];
@@ -813,7 +818,7 @@ __global__ __launch_bounds__(256) void k_prep(const KArgs a, int mode)
             if (tid == 0) {
                 dst[a.sub_count] = total;
                 if (pass == 0) {
-                    if (total > a.ws.max_tiles) {
+                    if (total > a.ws.max_tiles || ((mode & kPrepZeroLb) && total > lb_words)) {
                         bad |= PM_F_LAYOUT;
                         hdr[kHdrTiles] = 0u;
                     } else {
@@ -832,10 +837,7 @@ __global__ __launch_bounds__(256) void k_prep(const KArgs a, int mode)
     }
 
     if (mode & kPrepZeroLb) {
-        int64_t words = (int64_t)a.ws.pool_extent / a.tile + a.sub_count + 2;
-        if (words > a.ws.max_tiles)
-            words = a.ws.max_tiles;
-        for (int64_t i = gtid; i < words; i += gsize)
+        for (int64_t i = gtid; i < lb_words; i += gsize)
             a.ws.lb[i] = 0ull;
     }
 

@@ -381,13 +381,24 @@ def send_layout(counts, face=0.02, edge=0.002, corner=0.0005, extra=256):
     return base, cap
 
 
+def _int64(a):
+    """int64 view of an index array: numpy arrays and scalars, or torch
+    tensors (kept on their device)."""
+    if hasattr(a, "device") and hasattr(a, "dtype") and not isinstance(a, np.ndarray):
+        import torch
+        return a.to(torch.int64)
+    return np.asarray(a, dtype=np.int64)
+
+
 def morton3(i, j, k, bits=11):
-    """Z-order code of cell (i, j, k): bits of i, j, k interleaved, i lowest."""
-    code = np.zeros(np.shape(i), dtype=np.int64)
+    """Z-order code of cell (i, j, k): bits of i, j, k interleaved, i lowest.
+    Works on numpy arrays and on torch int64 tensors alike."""
+    i, j, k = _int64(i), _int64(j), _int64(k)
+    code = i * 0
     for b in range(bits):
-        code |= ((np.asarray(i, dtype=np.int64) >> b) & 1) << (3 * b)
-        code |= ((np.asarray(j, dtype=np.int64) >> b) & 1) << (3 * b + 1)
-        code |= ((np.asarray(k, dtype=np.int64) >> b) & 1) << (3 * b + 2)
+        code |= ((i >> b) & 1) << (3 * b)
+        code |= ((j >> b) & 1) << (3 * b + 1)
+        code |= ((k >> b) & 1) << (3 * b + 2)
     return code
 
 
@@ -395,26 +406,64 @@ def cell_key(i, j, k):
     """Sort key of the canonical order: the Z-order code of (i/2, j, k), then
     the parity of i, so that the smallest blocks are two cells long in x,
     the axis along which a stencil's two nodes share memory sectors."""
-    i = np.asarray(i, dtype=np.int64)
+    i = _int64(i)
     return morton3(i >> 1, j, k) * 2 + (i & 1)
 
 
+def _order_torch(pos, p, bnds, n, L, order, device):
+    """Owners and the stable order of build_pool computed with torch on
+    `device` (the same permutation as the numpy lexsort: the keys below
+    are unique up to ties, which a stable sort leaves in id order)."""
+    import torch
+    P = torch.from_numpy(np.ascontiguousarray(pos)).to(device)
+    idx = []
+    for a in range(3):
+        b = torch.from_numpy(np.ascontiguousarray(bnds[a])).to(device)
+        idx.append((torch.searchsorted(b, P[a].contiguous(), right=True) - 1)
+                   .clamp_(0, p[a] - 1))
+    s = idx[0] + p[0] * (idx[1] + p[1] * idx[2])
+    del idx
+    cell = [torch.floor(P[a] * (n / L)).to(torch.int64).clamp_(0, n - 1) for a in range(3)]
+    del P
+    bits = max(1, int(n - 1).bit_length())
+    if order == "rowmajor":
+        key = ((s * n + cell[2]) * n + cell[1]) * n + cell[0]
+    elif order == "morton":
+        key = (s << (3 * bits)) | morton3(cell[0], cell[1], cell[2])
+    else:
+        key = (s << (3 * bits + 1)) | cell_key(cell[0], cell[1], cell[2])
+    del cell
+    perm = torch.sort(key, stable=True).indices
+    del key
+    return s.cpu().numpy(), perm.cpu().numpy()
+
+
 def build_pool(pos, tau, ids, p, bnds, n, L=TWO_PI, slack=0.05, extra=1024,
-               vdtype=np.float64, order="canonical", shuffle_seed=None):
+               vdtype=np.float64, order="canonical", shuffle_seed=None, sort_device=None):
     """Pool with each particle in its owner's segment.  Canonical order: by
     subdomain, then cell_key of the cell, then id.  order="morton" uses the
     plain Z-order code of the cell, order="rowmajor" the cell (z, y, x);
     order="shuffled" permutes each segment of the canonical order with the
-    shuffle seed."""
+    shuffle seed.  sort_device: compute owners and the order with torch on
+    that device (same result; for pools of 2^26 and more particles), which
+    needs ids in drawing order (ids[i] == i)."""
     nsub = p[0] * p[1] * p[2]
-    s = owner(pos, bnds, p)
-    cell = [np.clip(np.floor(pos[a] * (n / L)).astype(np.int64), 0, n - 1) for a in range(3)]
-    if order == "rowmajor":
-        perm = np.lexsort((ids, cell[0], cell[1], cell[2], s))
-    elif order == "morton":
-        perm = np.lexsort((ids, morton3(cell[0], cell[1], cell[2]), s))
+    if sort_device is not None:
+        if not np.array_equal(ids[:16], np.arange(min(16, len(ids)), dtype=ids.dtype)):
+            raise ValueError("sort_device needs ids in drawing order")
+        s, perm = _order_torch(pos, p, bnds, n, L,
+                               "canonical" if order == "shuffled" else order, sort_device)
     else:
-        perm = np.lexsort((ids, cell_key(cell[0], cell[1], cell[2]), s))
+        s = owner(pos, bnds, p)
+        cell = [np.clip(np.floor(pos[a] * (n / L)).astype(np.int64), 0, n - 1)
+                for a in range(3)]
+        if order == "rowmajor":
+            perm = np.lexsort((ids, cell[0], cell[1], cell[2], s))
+        elif order == "morton":
+            perm = np.lexsort((ids, morton3(cell[0], cell[1], cell[2]), s))
+        else:
+            perm = np.lexsort((ids, cell_key(cell[0], cell[1], cell[2]), s))
+        del cell
     s_sorted = s[perm]
     counts = np.bincount(s_sorted, minlength=nsub).astype(np.int64)
     if order == "shuffled":
@@ -491,8 +540,12 @@ def dt_rule(field, tau_max, g, n, L=TWO_PI, kind="rule"):
 
 def make_workload(name, np_override=None, n_override=None, p_override=None,
                   order="canonical", field_backend="numpy", slack=0.05,
-                  extra=1024, kmax_override=None, k0_override=None):
-    """Build a named workload (optionally resized for tests)."""
+                  extra=1024, kmax_override=None, k0_override=None, sort_device=None,
+                  mode_override=None):
+    """Build a named workload (optionally resized for tests).  sort_device:
+    order the pool with torch on that device (the same pool, faster for
+    large workloads).  mode_override "f64" keeps tau in float64 for a
+    workload defined in mixed precision (which rounds the same draws)."""
     cfg = dict(CONFIGS[name])
     n = n_override or cfg["n"]
     p = tuple(p_override or cfg["p"])
@@ -519,14 +572,16 @@ def make_workload(name, np_override=None, n_override=None, p_override=None,
     npart = pos.shape[1]
     tau = draw_tau(rng(s_tau), npart, cfg["tau"])
     ids = np.arange(npart, dtype=np.uint64)
-    vdtype = np.float32 if cfg["mode"] == "mixed" else np.float64
+    mode = mode_override or cfg["mode"]
+    vdtype = np.float32 if mode == "mixed" else np.float64
     pool = build_pool(pos, tau, ids, p, bnds, n, L, slack=slack, extra=extra,
-                      vdtype=vdtype, order=order, shuffle_seed=s_shuf)
+                      vdtype=vdtype, order=order, shuffle_seed=s_shuf,
+                      sort_device=sort_device)
     if cfg["dt"] in ("rule", "rms"):
         dt = dt_rule(field, cfg["tau"][2], cfg["g"], n, L, kind=cfg["dt"])
     else:
         dt = float(cfg["dt"])
     return Workload(name=name, n=n, halo=cfg["halo"], L=L, p=p, bounds=bnds,
                     field=field, pool=pool, dt=dt, g=tuple(cfg["g"]),
-                    mode=cfg["mode"], steps=cfg["steps"],
+                    mode=mode, steps=cfg["steps"],
                     info=dict(k0=k0, kmax=kmax, np=npart, dist=cfg["dist"]))

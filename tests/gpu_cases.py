@@ -31,7 +31,8 @@ class Case:
         self.drag = drag
         self.wl = gen.make_workload(name, np_override=npart, n_override=n, p_override=p,
                                     order=order, slack=slack, extra=extra,
-                                    field_backend=field_backend)
+                                    field_backend=field_backend,
+                                    sort_device="cuda" if field_backend == "device" else None)
         wl = self.wl
         self.mode = mode or wl.mode
         self.dt = wl.dt * dt_scale
@@ -147,3 +148,54 @@ def compare_mid(got, ref, nseg, L, delta, what):
             g, r = getattr(got, name)[:, s].astype(np.float64), getattr(ref, name)[:, s]
             e = np.abs(g - r) / max(1.0, float(np.abs(r).max()) if r.size else 1.0)
             assert e.size == 0 or e.max() <= 1e-12, (what, name, q, e.max())
+
+
+def lockstep_migration(c, ctx, pin, out, send):
+    """Lock-step check of the migration: the device's own post-advance
+    records (the plain path's in-place advance of a copy of `pin`, bitwise
+    the fused step's advance) go through the oracle's sequential partition
+    and append (Sect. 2.3.3; unpacking, Sect. 3.2.2); the fused step's
+    `out` and `send` must equal the result record for record, bit for bit.
+    This checks classification, scan, pack, compaction and append exactly,
+    whatever the rounding of the advance."""
+    work = pm.DevicePool(pin.x.clone(), pin.v.clone(), pin.tau.clone(), pin.id.clone(),
+                         pin.base, pin.cap, pin.count.clone())
+    ctx.interp_advance(c.field, work, c.params)
+    assert ctx.get_status() == 0
+    adv = work.to_host()
+    del work
+    vdt = np.float32 if c.mode == "mixed" else np.float64
+    rout = gen.empty_pool(c.host.base, c.host.cap, vdt)
+    rsend = gen.empty_pool(c.sb, c.sc, vdt)
+    stay, f1 = oracle.partition(c.odc, adv, rout, rsend)
+    f2 = oracle.append(c.odc, rsend, stay, rout)
+    assert f1 == 0 and f2 == 0, (f1, f2)
+    delta = c.wl.L / c.wl.n
+    compare_pools(send.to_host(), rsend, c.dc.nsub * 27, c.wl.L, delta, exact=True,
+                  what="lock-step send")
+    compare_pools(out.to_host(), rout, c.dc.nsub, c.wl.L, delta, exact=True,
+                  what="lock-step out")
+    return int(rsend.count.sum())
+
+
+def valid_records(pool):
+    """(x, v as float64, tau as float64, id) of every valid record of a host
+    pool, in pool order."""
+    sl = [seg(pool, q) for q in range(len(pool.base))]
+    cat = lambda a: np.concatenate([a[..., s] for s in sl], axis=-1)  # noqa: E731
+    return cat(pool.x), cat(pool.v).astype(np.float64), cat(pool.tau).astype(np.float64), \
+        cat(pool.id)
+
+
+def per_id_errors(got, ref, L, delta, umax):
+    """Both pools hold the same ids (checked); returns the largest velocity
+    difference over |u|max and the largest position difference in cells
+    (periodic images folded), compared per id."""
+    gx, gv, _, gid = valid_records(got)
+    rx, rv, _, rid = valid_records(ref)
+    gi, ri = np.argsort(gid, kind="stable"), np.argsort(rid, kind="stable")
+    np.testing.assert_array_equal(gid[gi], rid[ri], err_msg="ids")
+    dx = np.abs(gx[:, gi] - rx[:, ri])
+    dx = np.minimum(dx, L - dx)
+    ev = float(np.abs(gv[:, gi] - rv[:, ri]).max(initial=0.0)) / umax
+    return ev, float(dx.max(initial=0.0)) / delta

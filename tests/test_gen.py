@@ -93,3 +93,17 @@ def test_tau_distributions():
     t = gen.draw_tau(g, 100000, ("loguniform", 0.01, 1.0))
     assert t.min() >= 0.01 and t.max() <= 1.0
     assert abs(np.median(np.log(t)) - math.log(0.1)) < 0.05
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("C2S", dict(np_override=60000, n_override=64)),
+    ("C4", dict(np_override=500, n_override=64)),
+    ("C5", dict(np_override=1 << 17, n_override=64))])
+@pytest.mark.parametrize("order", ["canonical", "morton", "rowmajor", "shuffled"])
+def test_torch_ordering_builds_the_same_pool(name, kw, order):
+    """The torch path of build_pool (run on the CPU here; on the GPU for the
+    large workloads) gives the numpy lexsort's pool record for record."""
+    a = gen.make_workload(name, order=order, **kw)
+    b = gen.make_workload(name, order=order, sort_device="cpu", **kw)
+    for f in ("x", "tau", "id", "base", "cap", "count"):
+        np.testing.assert_array_equal(getattr(a.pool, f), getattr(b.pool, f), err_msg=f)

@@ -5,7 +5,9 @@ gravity) and the same field cut into 8x8x8 periodic subdomains with a few
 percent migrating per step: one fused step on the GPU against one whole
 step of the CPU oracle on the same seeded input (the oracle runs in a few
 seconds at this size).  Counts, ids and their order must match exactly;
-positions and velocities to 1e-12.  The same at full size for the nonlinear
+positions and velocities to 1e-12; then the lock-step check: the oracle's
+partition and append on the device's own post-advance records must give the
+fused step's output bit for bit.  The same at full size for the nonlinear
 drag law, the MAC-staggered field and migration after each RK2 stage (its
 mid-step pool and send buffers too), each in its default launch shape.
 """
@@ -14,7 +16,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_cases import Case, compare_mid, compare_pools, say
+from gpu_cases import Case, compare_mid, compare_pools, lockstep_migration, say
 from paper_2604_11008_amd import gen, pm
 
 pytestmark = pytest.mark.gpu
@@ -47,6 +49,8 @@ def test_full_size_step_matches_the_oracle(name, shape):
     compare_pools(send.to_host(), ref_send, c.dc.nsub * 27, c.wl.L, delta, what="send")
     ex, ev = compare_pools(pout.to_host(), ref_out, c.dc.nsub, c.wl.L, delta, what="out")
     say(f"  migrants {int(ref_send.count.sum())}; max rel err x {ex:.2e} v {ev:.2e}")
+    lockstep_migration(c, ctx, pin, pout, send)
+    say("  lock-step migration exact")
 
 
 @pytest.mark.parametrize("name,drag,stagger", [("C2", "nonlinear", False),
@@ -120,3 +124,8 @@ def test_full_size_batched_workload_matches_the_oracle(name):
     compare_pools(send.to_host(), ref_send, c.dc.nsub * 27, c.wl.L, delta, what="send")
     ex, ev = compare_pools(pout.to_host(), ref_out, c.dc.nsub, c.wl.L, delta, what="out")
     say(f"  migrants {int(ref_send.count.sum())}; max rel err x {ex:.2e} v {ev:.2e}")
+    # the same migration on the device's own post-advance positions, bit for
+    # bit, so that exact parity does not rest on both sides rounding the
+    # advance alike
+    lockstep_migration(c, ctx, pin, pout, send)
+    say("  lock-step migration exact")

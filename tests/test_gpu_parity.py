@@ -247,9 +247,10 @@ def test_fused_equals_plain_bitwise(name, npart, n, p):
     assert_same_device_pools(send_a, send_b, c.dc.nsub * 27, "send")
 
 
-def test_every_launch_shape_gives_identical_results():
-    say("[test] launch shapes")
-    c = Case("C2S", 70000, 32, (4, 2, 2))
+@pytest.mark.parametrize("mode", ["f64", "mixed"])
+def test_every_launch_shape_gives_identical_results(mode):
+    say(f"[test] launch shapes, mode {mode}")
+    c = Case("C2S", 70000, 32, (4, 2, 2), mode=mode)
     c.params = pm.Params(0.015, c.g)
     pin = c.pin()
     ref_out, ref_send = None, None
@@ -383,6 +384,32 @@ def test_inconsistent_segment_table_is_a_no_op():
     pin.count[0] = int(c.host.count[0])
     ctx.step(c.field, c.dc, pin, out, send, c.params)
     assert ctx.get_status() == 0
+
+
+def test_overlapping_segments_raise_layout():
+    """Four segments over the same 4096 records, stepped with 1024-record
+    tiles: 16 tiles, more than non-overlapping segments of that extent can
+    give (4096/1024 + 4 + 2 look-back words are cleared), so the step must
+    flag the layout and do nothing rather than read stale look-back words."""
+    say("[test] overlapping segments")
+    c = Case("C2S", 8000, 32, (2, 2, 1))
+    n = 4096
+    host = gen.empty_pool(np.zeros(4, dtype=np.int64), np.full(4, n, dtype=np.int64))
+    host.x[:, :] = c.host.x[:, :n]
+    host.v[:, :] = c.host.v[:, :n]
+    host.tau[:] = c.host.tau[:n]
+    host.id[:] = c.host.id[:n]
+    host.count[:] = n
+    pin = pm.DevicePool.from_host(host, c.dev)
+    send = c.send()
+    q = n // 4
+    out = pm.DevicePool.empty(np.arange(4) * q, np.full(4, q), device=c.dev, size=n)
+    ctx = pm.Context(n, send.size, 4, device=c.dev)
+    ctx.set_tuning(256, 4)
+    out.count.fill_(-7)
+    ctx.step(c.field, c.dc, pin, out, send, c.params)
+    assert ctx.get_status() & pm.LAYOUT
+    assert int(out.count[0].item()) == -7
 
 
 # ---------------------------------------------------------------------------
