@@ -295,6 +295,37 @@ pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
                   const pm_particles *in, pm_particles *out,
                   pm_sendbufs *send, const pm_params *params, void *stream);
 
+/* Bytes of the fixed device array pm_step_noalloc works in (per device). */
+#define PM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* pm_step for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  It needs no context
+ * and no workspace: its scratch (the header words, tile and staging tables,
+ * look-back words and the leavers' staging area that pm_step keeps in the
+ * workspace) is a fixed array of PM_NOALLOC_SCRATCH_BYTES in device memory
+ * of the library, one per device, held until the process ends.  It calls no
+ * allocating routine and queues only kernels, so a caller may capture it.
+ *
+ * Arguments as in pm_step; pool_extent is the number of records the arrays
+ * of `in` and `out` hold (every segment must end within it), send_extent
+ * that of `send`.  flags: caller-owned device memory of one uint32 that
+ * receives this step's flag bits (PM_F_*) when its work is done.  Results
+ * are bitwise those of pm_step with a context of the same extents and its
+ * default launch shape.  Sizes whose scratch would exceed the array
+ * (pm_workspace_bytes less the plain path's 4 bytes per pool record: about
+ * 137 bytes per send-buffer record, 8 bytes per 256 pool records and 100 KB,
+ * e.g. a pool of 2^24 records in 512 subdomains with up to 470,000
+ * send-buffer records) are rejected with PM_ERR_ARG before anything is
+ * queued.  Every call on a device uses that device's one array: calls that
+ * overlap on one device (other streams, other threads) race and must not
+ * be made; each call clears the flag word on entry, and the other scratch
+ * contents are rebuilt by the step itself. */
+pm_status pm_step_noalloc(const pm_field *field, const pm_decomp *decomp,
+                          const pm_particles *in, pm_particles *out,
+                          pm_sendbufs *send, const pm_params *params,
+                          int64_t pool_extent, int64_t send_extent,
+                          uint32_t *flags, void *stream);
+
 /* Synchronise `stream`, return the flag word (PM_F_*) and clear it.
  * The capacities that would have sufficed after an overflow need no
  * out-parameter: the counts the step writes are exact whatever the

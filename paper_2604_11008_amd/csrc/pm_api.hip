@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -50,9 +51,10 @@ struct WsLayout {
 };
 
 // Device workspace: header words, per-segment tables, one look-back word per
-// tile, the plain path's stayer slots, and the staging area of the leavers
+// tile, the plain path's stayer slots (slot = false: none, for a workspace
+// that serves the fused step only), and the staging area of the leavers
 // (one record per send-buffer slot, 8-byte fields, plus a direction byte).
-WsLayout ws_layout(int64_t pool_extent, int64_t send_extent, int32_t nsub)
+WsLayout ws_layout(int64_t pool_extent, int64_t send_extent, int32_t nsub, bool slot = true)
 {
     WsLayout L{};
     size_t o = 0;
@@ -71,7 +73,8 @@ WsLayout ws_layout(int64_t pool_extent, int64_t send_extent, int32_t nsub)
     L.lb = o;
     o += align256((size_t)L.max_tiles * sizeof(uint64_t));
     L.slot = o;
-    o += align256((size_t)std::max<int64_t>(pool_extent, 1) * sizeof(uint32_t));
+    if (slot)
+        o += align256((size_t)std::max<int64_t>(pool_extent, 1) * sizeof(uint32_t));
     // every segment's staging area is rounded up to a multiple of 16 records
     L.stg_extent = send_extent + 16 * (int64_t)ns + 16;
     L.stg = o;
@@ -79,6 +82,37 @@ WsLayout ws_layout(int64_t pool_extent, int64_t send_extent, int32_t nsub)
     o += 17 * align256((size_t)L.stg_extent * 8) + align256((size_t)L.stg_extent);
     L.total = o;
     return L;
+}
+
+// Device pointers of a workspace at w laid out by L, and its extents.
+void bind_ws(pm::DWS &ws, char *w, const WsLayout &L, int64_t pool_extent,
+             int64_t send_extent, bool slot)
+{
+    ws.hdr = (uint32_t *)(w + L.hdr);
+    ws.tile_start = (int64_t *)(w + L.tile_start);
+    ws.stay = (int64_t *)(w + L.stay);
+    ws.migtot = (int64_t *)(w + L.migtot);
+    ws.stg_start = (int64_t *)(w + L.stg_start);
+    ws.lb = (uint64_t *)(w + L.lb);
+    ws.slot = slot ? (uint32_t *)(w + L.slot) : nullptr;
+    const size_t fs = align256((size_t)L.stg_extent * 8);
+    char *g = w + L.stg;
+    for (int c = 0; c < 3; ++c) {
+        ws.stg_x[c] = (double *)(g + c * fs);
+        ws.stg_v[c] = (double *)(g + (3 + c) * fs);
+    }
+    ws.stg_tau = (double *)(g + 6 * fs);
+    ws.stg_id = (uint64_t *)(g + 7 * fs);
+    for (int c = 0; c < 3; ++c) {
+        ws.stg_xs[c] = (double *)(g + (8 + c) * fs);
+        ws.stg_vs[c] = (double *)(g + (11 + c) * fs);
+        ws.stg_a[c] = (double *)(g + (14 + c) * fs);
+    }
+    ws.stg_d = (uint8_t *)(g + 17 * fs);
+    ws.max_tiles = L.max_tiles;
+    ws.pool_extent = pool_extent;
+    ws.send_extent = send_extent;
+    ws.stg_extent = L.stg_extent;
 }
 
 struct GraphEntry {
@@ -474,32 +508,7 @@ pm_status pm_create(pm_ctx **out, void *workspace, size_t ws_bytes, int64_t pool
         delete ctx;
         return hip_error(e, "device query");
     }
-    char *w = (char *)workspace;
-    ctx->ws.hdr = (uint32_t *)(w + L.hdr);
-    ctx->ws.tile_start = (int64_t *)(w + L.tile_start);
-    ctx->ws.stay = (int64_t *)(w + L.stay);
-    ctx->ws.migtot = (int64_t *)(w + L.migtot);
-    ctx->ws.stg_start = (int64_t *)(w + L.stg_start);
-    ctx->ws.lb = (uint64_t *)(w + L.lb);
-    ctx->ws.slot = (uint32_t *)(w + L.slot);
-    const size_t fs = align256((size_t)L.stg_extent * 8);
-    char *g = w + L.stg;
-    for (int c = 0; c < 3; ++c) {
-        ctx->ws.stg_x[c] = (double *)(g + c * fs);
-        ctx->ws.stg_v[c] = (double *)(g + (3 + c) * fs);
-    }
-    ctx->ws.stg_tau = (double *)(g + 6 * fs);
-    ctx->ws.stg_id = (uint64_t *)(g + 7 * fs);
-    for (int c = 0; c < 3; ++c) {
-        ctx->ws.stg_xs[c] = (double *)(g + (8 + c) * fs);
-        ctx->ws.stg_vs[c] = (double *)(g + (11 + c) * fs);
-        ctx->ws.stg_a[c] = (double *)(g + (14 + c) * fs);
-    }
-    ctx->ws.stg_d = (uint8_t *)(g + 17 * fs);
-    ctx->ws.max_tiles = L.max_tiles;
-    ctx->ws.pool_extent = pool_extent;
-    ctx->ws.send_extent = send_extent;
-    ctx->ws.stg_extent = L.stg_extent;
+    bind_ws(ctx->ws, (char *)workspace, L, pool_extent, send_extent, true);
     ctx->nsub_max = nsub;
     // start from a clean header, tables and look-back state
     e = hipMemset(workspace, 0, L.slot);
@@ -801,6 +810,108 @@ pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
         pm::KArgs kk = k;
         return queue_step(ctx, kk, mixed, cs, false);
     });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// pm_step_noalloc: pm_step with its scratch in a fixed device array of the
+// library instead of a caller's workspace
+// ---------------------------------------------------------------------------
+
+// The scratch of pm_step_noalloc (header words, tile and staging tables,
+// look-back words, the leavers' staging area): one copy per device, zero at
+// load, shared by every call on that device.  In host code this name is not
+// a device address; the address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) unsigned char scratch[PM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+
+struct NoAllocDevice {
+    bool ready;
+    int cus;
+    char *ptr;  // device address of `scratch` on this device
+};
+
+NoAllocDevice g_noalloc[kNoAllocDevices];
+std::mutex g_noalloc_mu;
+
+// The current device's scratch address and CU count, looked up once per
+// device (with that device current).
+pm_status noalloc_device(NoAllocDevice **out)
+{
+    int dev = 0;
+    PM_HIP(hipGetDevice(&dev), "device query");
+    if (dev < 0 || dev >= kNoAllocDevices)
+        return arg_error("device %d is beyond the %d that pm_step_noalloc serves", dev,
+                         kNoAllocDevices);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    NoAllocDevice &d = g_noalloc[dev];
+    if (!d.ready) {
+        void *p = nullptr;
+        PM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+        if (!p || ((uintptr_t)p & 255u) != 0)
+            return hip_error(hipErrorInvalidSymbol, "scratch address");
+        int cus = 0;
+        PM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+               "device query");
+        d.cus = cus;
+        d.ptr = (char *)p;
+        d.ready = true;
+    }
+    *out = &d;
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_step_noalloc(const pm_field *field, const pm_decomp *decomp,
+                          const pm_particles *in, pm_particles *out, pm_sendbufs *send,
+                          const pm_params *params, int64_t pool_extent, int64_t send_extent,
+                          uint32_t *flags, void *stream)
+{
+    if (!flags)
+        return arg_error("flags is NULL");
+    if (!in)
+        return arg_error("in is NULL");
+    if (in->nsub < 1 || in->nsub > PM_MAX_NSUB)
+        return arg_error("nsub = %d not in 1..%d", in->nsub, PM_MAX_NSUB);
+    if (pool_extent < 0 || pool_extent > kMaxExtent || send_extent < 0 ||
+        send_extent > kMaxExtent)
+        return arg_error("pool or send extent out of range (0..2^34)");
+    const WsLayout L = ws_layout(pool_extent, send_extent, in->nsub, false);
+    if (L.total > PM_NOALLOC_SCRATCH_BYTES)
+        return arg_error("pm_step_noalloc: %lld pool records, %lld send records and %d "
+                         "subdomains need %zu bytes of scratch, more than its %zu",
+                         (long long)pool_extent, (long long)send_extent, in->nsub, L.total,
+                         (size_t)PM_NOALLOC_SCRATCH_BYTES);
+    NoAllocDevice *d = nullptr;
+    pm_status s = noalloc_device(&d);
+    if (s)
+        return s;
+    // host-side settings only (the default launch shape; no graphs, no
+    // timing): nothing here allocates
+    pm_ctx ctx;
+    ctx.cus = d->cus;
+    ctx.nsub_max = in->nsub;
+    bind_ws(ctx.ws, d->ptr, L, pool_extent, send_extent, false);
+    pm::KArgs k;
+    bool mixed = false;
+    s = step_args(&ctx, field, decomp, in, out, send, params, k, mixed);
+    if (s)
+        return s;
+    hipStream_t st = (hipStream_t)stream;
+    // the array keeps the last call's contents: start without its flags
+    PM_HIP(pm::launch_flags_move(ctx.ws.hdr, nullptr, st), "flags launch");
+    s = queue_step(&ctx, k, mixed, st, false);
+    if (s)
+        return s;
+    PM_HIP(pm::launch_flags_move(ctx.ws.hdr, flags, st), "flags launch");
+    return PM_OK;
 }
 
 pm_status pm_get_status(pm_ctx *ctx, void *stream, uint32_t *flags)

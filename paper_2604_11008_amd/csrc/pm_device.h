@@ -1579,6 +1579,19 @@ __global__ __launch_bounds__(256) void k_fill(uint64_t *p, int64_t words)
         p[i] = 0ull;
 }
 
+// The flag word of a workspace header handed to the caller (dst, when not
+// NULL) and cleared, so that the next step starts without flags.  Runs
+// after every other kernel of a step on the same stream.
+__global__ __launch_bounds__(64) void k_flags_move(uint32_t *hdr, uint32_t *dst)
+{
+    if (threadIdx.x == 0) {
+        const uint32_t f = flags_now(hdr);
+        if (dst)
+            *dst = f;
+        __hip_atomic_store(hdr + kHdrFlags, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // migration after each RK2 stage (the paper's scheme, Sect. 3.2.2): the
 // mid-step record carries X_n, V_n, X*, V* and the stage-1 acceleration a

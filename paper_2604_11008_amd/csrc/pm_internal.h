@@ -147,6 +147,8 @@ hipError_t launch_touch(const KArgs &a, bool mixed, uint64_t *bitmap, hipStream_
 hipError_t launch_popcount(const uint64_t *bitmap, int64_t words,
                            unsigned long long *out, hipStream_t st);
 hipError_t launch_fill(uint64_t *p, int64_t words, hipStream_t st);
+// hdr's flag word into *dst (dst may be NULL), then cleared.
+hipError_t launch_flags_move(uint32_t *hdr, uint32_t *dst, hipStream_t st);
 
 // Workgroups per CU that fit for a launch shape of the fused kernel.
 int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, bool stagger);

@@ -161,6 +161,12 @@ hipError_t launch_fill(uint64_t *p, int64_t words, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_flags_move(uint32_t *hdr, uint32_t *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flags_move, dim3(1), dim3(64), 0, st, hdr, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_step(const KArgs &a, Shape sh, bool mixed, int grid, hipStream_t st)
 {
     return mixed ? launch_step_f32(a, sh, grid, st) : launch_step_f64(a, sh, grid, st);

@@ -100,6 +100,7 @@ def lib():
             "pm_compact_append": ([vp, vp, vp, vp, vp, i32, i32, vp], C.c_int),
             "pm_step": ([vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "pm_step_staged": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+            "pm_step_noalloc": ([vp, vp, vp, vp, vp, vp, i64, i64, vp, vp], C.c_int),
             "pm_get_status": ([vp, vp, vp], C.c_int),
             "pm_set_tuning": ([vp, vp], C.c_int),
             "pm_get_tuning": ([vp, vp], C.c_int),
@@ -490,6 +491,22 @@ class Context:
                                       C.byref(params.c), _p(bm), words * 64,
                                       _stream(stream), C.byref(out)))
         return int(out.value)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def step_noalloc(field, decomp, pin, pout, send, params, flags, stream=None):
+    """pm_step_noalloc: the fused step with the library's fixed device scratch
+    instead of a context and workspace.  flags: a device int32 tensor of one
+    element that receives the step's flag bits."""
+    if flags.dtype != torch.int32 or flags.numel() != 1 or not flags.is_cuda:
+        raise PMError("flags must be a device int32 tensor of one element")
+    pc, oc, sc = pin.particles(), pout.particles(), send.sendbufs()
+    _check(lib().pm_step_noalloc(C.byref(field.c), C.byref(decomp.c), C.byref(pc),
+                                 C.byref(oc), C.byref(sc), C.byref(params.c),
+                                 min(pin.size, pout.size), send.size, _p(flags),
+                                 _stream(stream)))
 
 
 def flag_names(f):

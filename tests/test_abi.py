@@ -122,3 +122,24 @@ def test_binding_passes_the_row_pointers_of_each_array():
             want = [getattr(st, name)[a].data_ptr() for a in range(3)]
             assert [getattr(spc, name)[a] for a in range(3)] == want
             assert [getattr(ssc, name)[a] for a in range(3)] == want
+
+
+def test_noalloc_argument_errors_without_a_device():
+    """pm_step_noalloc checks its flags pointer, subdomain count and the size
+    of the scratch its extents need before it touches a device."""
+    from paper_2604_11008_amd import pm
+    lib = pm.lib()
+    parts = pm._Particles()
+    parts.nsub = 8
+    one = ctypes.c_uint32()
+    assert lib.pm_step_noalloc(None, None, ctypes.byref(parts), None, None, None, 100, 100,
+                               None, None) == 1
+    assert b"flags" in lib.pm_last_error()
+    # 10^6 send-buffer records need about 137 MB of scratch, more than its 64 MiB
+    assert lib.pm_step_noalloc(None, None, ctypes.byref(parts), None, None, None, 1 << 20,
+                               1_000_000, ctypes.byref(one), None) == 1
+    assert b"scratch" in lib.pm_last_error()
+    parts.nsub = 0
+    assert lib.pm_step_noalloc(None, None, ctypes.byref(parts), None, None, None, 100, 100,
+                               ctypes.byref(one), None) == 1
+    assert b"nsub" in lib.pm_last_error()
