@@ -106,6 +106,10 @@ def parse():
                     help="run on a new (default-priority) stream instead of the null stream")
     ap.add_argument("--plain-per-sub", action="store_true",
                     help="time the plain path launched once per subdomain")
+    ap.add_argument("--cpu-delegated", action="store_true",
+                    help="time the CPU-delegated exchange of the paper's comparison: the "
+                         "17-array records device->host, the oracle's sequential pack and "
+                         "unpack on one core, host->device")
     return ap.parse_args()
 
 
@@ -282,6 +286,64 @@ def link_gbps(torch, dev, nbytes=1 << 28):
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def delegated_transfers(ctx, field, p, params, dev):
+    """Device side of the CPU-delegated exchange (the paper's comparison in
+    Sect. 3.2.2): the state advanced by one step on a copy, then its
+    17-array record (x, v, x*, v*, a, tau, id: 136 bytes per particle in
+    float64) copied device -> pinned host and back, timed.  Returns the
+    advanced records on the host for the oracle's pack and unpack."""
+    import torch
+    from paper_2604_11008_amd import pm
+    work = pm.DevicePool(p.x.clone(), p.v.clone(), p.tau.clone(), p.id.clone(), p.base,
+                         p.cap, p.count.clone())
+    ctx.interp_advance(field, work, params)
+    n = work.x.shape[1]
+    dev17 = torch.empty((17, n), dtype=torch.float64, device=dev)
+    dev17[0:3] = work.x
+    dev17[3:6] = work.v.double()
+    dev17[6:9] = work.x
+    dev17[9:15] = work.v.double().repeat(2, 1)
+    dev17[15] = work.tau.double()
+    dev17[16] = work.id.view(torch.float64)
+    host17 = torch.empty((17, n), dtype=torch.float64, pin_memory=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    host17.copy_(dev17)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dev17.copy_(host17)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    if ctx.get_status():
+        raise SystemExit("flags in the delegated-exchange advance")
+    host = work.to_host()
+    del work, dev17, host17
+    return {"records": int(host.count.sum()), "bytes": 17 * 8 * n,
+            "d2h_ms": (t1 - t0) * 1e3, "h2d_ms": (t2 - t1) * 1e3, "host_state": host}
+
+
+def delegated_pack_unpack(wl, host):
+    """Host side of the CPU-delegated exchange: the oracle's sequential pack
+    (classification and per-direction counters) and unpack (compaction and
+    receive) of the advanced records, one core, timed."""
+    import oracle
+    od = oracle.Decomp(wl.p, wl.bounds)
+    pool = gen.Pool(x=host.x, v=host.v.astype(np.float64), tau=host.tau.astype(np.float64),
+                    id=host.id, base=host.base, cap=host.cap, count=host.count)
+    sb, sc = gen.send_layout(pool.count, face=0.05, edge=0.01, corner=0.005)
+    out = gen.empty_pool(pool.base, pool.cap)
+    send = gen.empty_pool(sb, sc)
+    t0 = time.perf_counter()
+    stay, f1 = oracle.partition(od, pool, out, send)
+    t1 = time.perf_counter()
+    f2 = oracle.append(od, send, stay, out)
+    t2 = time.perf_counter()
+    if f1 or f2:
+        raise SystemExit(f"oracle flags {f1 | f2} in the delegated exchange")
+    return {"pack_ms": (t1 - t0) * 1e3, "unpack_ms": (t2 - t1) * 1e3,
+            "migrants": int(send.count.sum())}
 
 
 # ----------------------------------------------------------------------------
@@ -489,6 +551,8 @@ def run(args, wl, dev, field, dc, start, pool, sb, sc, mixed, plain, label):
         if f:
             raise SystemExit(f"{label}: flags after graph steps: {pm.flag_names(f)}")
         res["graph_ms_per_step"] = round((tg1 - tg0) * 1e3 / args.steps, 5)
+    if args.cpu_delegated and label == args.first_mode:
+        res["delegated"] = delegated_transfers(ctx, field, pa, params, dev)
     if plain:
         # the plain path: three calls per step over all subdomains, advancing
         # in place on a copy so that the step's input stays intact
@@ -595,6 +659,7 @@ def main():
         f"{dc.nsub} subdomains, dt={wl.dt:.4g}, gen {t_gen:.1f}s, runs {modes}")
 
     plain_on = args.plain == "on" or (args.plain == "auto" and precision == "both")
+    args.first_mode = modes[0]
     results = {}
     for mode in modes:
         if mode == "f64":
@@ -639,6 +704,18 @@ def main():
         triad = single_core_triad_gbps()
         model = accounting.cpu_delegated_model(1, accounting.record_bytes(modes[0]), npart,
                                                min(h2d, d2h), triad)
+        delegated = None
+        if "delegated" in head:
+            d = head.pop("delegated")
+            pu = delegated_pack_unpack(wl, d.pop("host_state"))
+            d.update(pu)
+            d["total_ms"] = d["d2h_ms"] + d["pack_ms"] + d["unpack_ms"] + d["h2d_ms"]
+            d["what"] = ("one exchange as the CPU-delegated scheme does it: the 17 float64 "
+                         "arrays of every record device->host (pinned), the oracle's "
+                         "sequential pack and unpack of the advanced records (8 values "
+                         "each) on one core, the 17 arrays host->device")
+            delegated = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+            log(f"CPU-delegated exchange: {delegated}")
         cpu = {"value": round(m * steps / el, 1), "unit": "particles/s", "cores": 1,
                "kind": "oracle", "host": host_cpu(),
                "sample": f"{steps} whole oracle steps (sequential FP64, one thread, "
@@ -650,6 +727,8 @@ def main():
                    "single_core_triad_GBps": round(triad, 1),
                    "ms_per_migration": round(model["total_ms"], 2),
                    "gpu_fused_step_ms": round(head["ms_per_step"], 4)}}
+        if delegated is not None:
+            cpu["cpu_delegated_measured"] = delegated
     else:
         for r in results.values():
             r.pop("samples", None)

@@ -96,16 +96,23 @@ def _kernel_value(means, substr, counter, largest=False):
     return max(vals)[0] if largest else vals[0][0]
 
 
+COPY_DISPATCHES = 13  # bench.py's copy probe: 3 warm-up copies and 10 timed ones
+
+
 def copy_reading(path, counter):
-    """The counter's reading (KiB) for the 1 GiB copy: the largest copy dispatch."""
-    best = 0.0
-    for r in _rows(path):
-        if COPY_KERNEL in _get(r, "Kernel_Name", "KERNEL_NAME", "Kernel-Name") and \
-                _get(r, "Counter_Name", "COUNTER_NAME") == counter:
-            best = max(best, float(_get(r, "Counter_Value", "COUNTER_VALUE")))
-    if best <= 0:
+    """The counter's reading (KiB) for the 1 GiB copy: the median over the
+    run's last COPY_DISPATCHES device copies, which are bench.py's copy probe
+    (run after every pool copy; the counter runs pass --no-cpu, so no host
+    copy follows it)."""
+    rows = [r for r in _rows(path)
+            if COPY_KERNEL in _get(r, "Kernel_Name", "KERNEL_NAME", "Kernel-Name") and
+            _get(r, "Counter_Name", "COUNTER_NAME") == counter]
+    rows.sort(key=lambda r: int(_get(r, "Dispatch_Id", "DISPATCH_ID")))
+    vals = sorted(float(_get(r, "Counter_Value", "COUNTER_VALUE"))
+                  for r in rows[-COPY_DISPATCHES:])
+    if not vals or vals[len(vals) // 2] <= 0:
         raise KeyError(f"no {counter} reading for the copy kernel")
-    return best
+    return vals[len(vals) // 2]
 
 
 def traffic(fetch_csv, write_csv, kernel_substr):
