@@ -481,10 +481,11 @@ struct TileLds {
     TileHead h;
 };
 
-// Segment of ticket q: the largest k with tile_start[k] <= q.
-__device__ __forceinline__ void locate(const KArgs &a, int tile, int64_t q, TileHead &h)
+// Segment of ticket q: the largest k with tile_start[k] <= q, searched in ts
+// (the workspace's tile table, or a copy of it in LDS).
+__device__ __forceinline__ void locate(const KArgs &a, int tile, int64_t q, TileHead &h,
+                                       const int64_t *ts)
 {
-    const int64_t *ts = a.ws.tile_start;
     int lo = 0, hi = a.sub_count;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -895,7 +896,7 @@ __global__ __launch_bounds__(256) void k_prep(const KArgs a, int mode)
 // of workgroups 0..xg-1 gives.
 template <int WG, int ITEMS>
 __device__ __forceinline__ bool next_tile(const KArgs &a, TileLds<WG, ITEMS> &L,
-                                          int64_t total)
+                                          int64_t total, const int64_t *ts)
 {
     if (threadIdx.x == 0) {
         int64_t q;
@@ -911,10 +912,26 @@ __device__ __forceinline__ bool next_tile(const KArgs &a, TileLds<WG, ITEMS> &L,
         }
         L.h.q = q < total ? q : total;
         if (q < total)
-            locate(a, a.tile, q, L.h);
+            locate(a, a.tile, q, L.h, ts);
     }
     __syncthreads();
     return L.h.q < total;
+}
+
+// The tile table of the fused kernel's segment range, copied into LDS when it
+// fits (every ticket's segment is found by a binary search over it: in LDS
+// the search costs no round trips to the L2).
+constexpr int kTileTableLds = 1024;
+
+template <int WG>
+__device__ __forceinline__ const int64_t *tile_table(const KArgs &a, int64_t *lds)
+{
+    if (a.sub_count + 1 > kTileTableLds)
+        return a.ws.tile_start;
+    for (int i = threadIdx.x; i <= a.sub_count; i += WG)
+        lds[i] = a.ws.tile_start[i];
+    __syncthreads();
+    return lds;
 }
 
 // Records of a tile between its advance and its scatter.  Each thread keeps
@@ -991,6 +1008,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ?
     constexpr int NW = WG / 64;
     __shared__ TileLds<WG, ITEMS> L[2];
     __shared__ TileStash<WG, ITEMS, FT> S;
+    __shared__ int64_t TT[kTileTableLds];
     uint32_t *hdr = a.ws.hdr;
     if (flags_now(hdr) & PM_F_LAYOUT)
         return;
@@ -999,8 +1017,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ?
     uint32_t fl = 0;
     int cur = 0;
     bool pend = false;
+    const int64_t *ts = tile_table<WG>(a, TT);
 
-    while (next_tile<WG, ITEMS>(a, L[cur], total)) {
+    while (next_tile<WG, ITEMS>(a, L[cur], total, ts)) {
         TileLds<WG, ITEMS> &C = L[cur];
         const int s = C.h.s;
         const int64_t first = C.h.first;
@@ -1100,7 +1119,7 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs a)
     uint32_t fl = 0;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
         if (tid == 0)
-            locate(a, a.tile, q, H);
+            locate(a, a.tile, q, H, a.ws.tile_start);
         __syncthreads();
         const int64_t first = H.first;
         const int nitems = H.nitems;
@@ -1150,7 +1169,7 @@ __global__ __launch_bounds__(WG) void k_classify(const KArgs a)
     const int tid = threadIdx.x, w = tid >> 6;
     uint32_t fl = 0;
 
-    while (next_tile<WG, ITEMS>(a, L, total)) {
+    while (next_tile<WG, ITEMS>(a, L, total, a.ws.tile_start)) {
         const int s = L.h.s;
         const int64_t first = L.h.first;
         const int nitems = L.h.nitems;
@@ -1386,7 +1405,7 @@ __global__ __launch_bounds__(WG) void k_compact(const KArgs a)
     uint32_t fl = 0;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
         if (tid == 0)
-            locate(a, a.tile, q, H);
+            locate(a, a.tile, q, H, a.ws.tile_start);
         __syncthreads();
         const int s = H.s;
         const int64_t first = H.first;
@@ -1523,7 +1542,7 @@ __global__ __launch_bounds__(256) void k_touch(const KArgs a, uint64_t *bits)
     uint32_t fl = 0;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
         TileHead h;
-        locate(a, a.tile, q, h);
+        locate(a, a.tile, q, h, a.ws.tile_start);
         for (int i = threadIdx.x; i < h.nitems; i += 256) {
             const int64_t p = h.first + i;
             double X[2][3];
@@ -1769,7 +1788,7 @@ __global__ __launch_bounds__(WG) void k_stage(const KArgs a)
     int cur = 0;
     bool pend = false;
 
-    while (next_tile<WG, ITEMS>(a, L[cur], total)) {
+    while (next_tile<WG, ITEMS>(a, L[cur], total, a.ws.tile_start)) {
         TileLds<WG, ITEMS> &C = L[cur];
         const int s = C.h.s;
         const int64_t first = C.h.first;

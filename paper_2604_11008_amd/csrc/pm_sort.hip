@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kSortWG) void k_sort_keys(const KArgs a, DSort s)
         return;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
         TileHead h;
-        locate(a, kSortTile, q, h);
+        locate(a, kSortTile, q, h, a.ws.tile_start);
         for (int i = threadIdx.x; i < h.nitems; i += kSortWG) {
             const int64_t p = h.first + i;
             const int ci = cell_of(a.in.x[0][p], a.f.r[0], a.f.n[0]);
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kSortWG) void k_sort_hist(const KArgs a, DSort s, i
     const int tid = threadIdx.x;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
         TileHead h;
-        locate(a, kSortTile, q, h);
+        locate(a, kSortTile, q, h, a.ws.tile_start);
         cnt[tid] = 0;
         __syncthreads();
         for (int i = tid; i < h.nitems; i += kSortWG) {
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kSortWG) void k_sort_scatter(const KArgs a, DSort s
     uint32_t fl = 0;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
         TileHead h;
-        locate(a, kSortTile, q, h);
+        locate(a, kSortTile, q, h, a.ws.tile_start);
         const int64_t lo = a.in.base[h.s], hi = lo + a.in.count[h.s];
         run[tid] = s.off[q * 256 + tid];
 #pragma unroll
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kSortWG) void k_sort_gather(const KArgs a, DSort s,
     uint32_t fl = 0;
     for (int64_t q = blockIdx.x; q < total; q += gridDim.x) {
         TileHead h;
-        locate(a, kSortTile, q, h);
+        locate(a, kSortTile, q, h, a.ws.tile_start);
         const int64_t lo = a.in.base[h.s], hi = lo + a.in.count[h.s];
         const int64_t obase = a.out.base[h.s], ocap = a.out.cap[h.s];
         for (int i = threadIdx.x; i < h.nitems; i += kSortWG) {
