@@ -6,7 +6,10 @@ Gaussian blobs of two cells, 30% uniform), tau log-uniform in [0.01, 1],
 8x8x8 subdomains, dt giving at most half a cell per step.  It runs in
 float64 (field, velocities, tau: `value`, the paper's precision) and in the
 mixed form (float32 field, velocities and tau; float64 positions and
-ownership), and times the plain float64 three-call path beside them.
+ownership), and times the plain float64 three-call path beside them; then
+both forms again from the same start with the field stored node-interleaved
+(the three components of a node next to each other), whose final states
+must be bitwise those of the split runs.
 
 A step is the whole hot path over every particle: interpolation at two RK2
 stages, the Heun drag update, classification, scan, pack/compact and the
@@ -72,6 +75,12 @@ def parse():
     ap.add_argument("--stagger", action="store_true",
                     help="read the field as MAC-staggered (component c on the faces "
                          "normal to axis c)")
+    ap.add_argument("--layout", default="auto",
+                    choices=["auto", "split", "interleaved", "both"],
+                    help="field storage: one array per component (split), the three "
+                         "components of a node interleaved, or both (split as the value, "
+                         "then interleaved from the same start); auto: both for the "
+                         "1024^3 workload, else split")
     ap.add_argument("--staged", action="store_true",
                     help="migrate after each RK2 stage (the paper's scheme) instead of once "
                          "per step")
@@ -350,6 +359,26 @@ def delegated_pack_unpack(wl, host):
 # one run: a precision, its pools, its timed steps
 # ----------------------------------------------------------------------------
 
+def state_digest(p):
+    """Order- and bit-sensitive 64-bit digest of a device pool's valid records
+    (x, v, tau, id), computed on the device."""
+    import torch
+    size = p.x.shape[1]
+    cnt = torch.minimum(p.count, p.cap)
+    edge = torch.zeros(size + 1, dtype=torch.int32, device=p.x.device)
+    edge.index_add_(0, p.base, torch.ones_like(p.base, dtype=torch.int32))
+    edge.index_add_(0, p.base + cnt, -torch.ones_like(p.base, dtype=torch.int32))
+    valid = edge.cumsum(0)[:size] > 0
+    w = 2 * torch.arange(size, device=p.x.device)[valid] + 1
+    d = 0
+    for t in (p.x, p.v, p.tau.view(1, -1), p.id.view(1, -1)):
+        bits = t.view(torch.int64) if t.element_size() == 8 else \
+            t.view(torch.int32).to(torch.int64)
+        for r in range(bits.shape[0]):
+            d = (d * 1000003 + int((bits[r][valid] * w).sum().item())) & ((1 << 64) - 1)
+    return f"{d:016x}"
+
+
 def run(args, wl, dev, field, dc, start, pool, sb, sc, mixed, plain, label):
     """Device samples for the CPU-baseline leg (untimed steps from the start
     state), warm-up, the timed steps with per-launch kernel times, graph
@@ -451,6 +480,7 @@ def run(args, wl, dev, field, dc, start, pool, sb, sc, mixed, plain, label):
     f = ctx.get_status()
     if f:
         raise SystemExit(f"{label}: flags after the timed steps: {pm.flag_names(f)}")
+    res["state_digest"] = state_digest(pa)
     ms_step = (t1 - t0) * 1e3 / args.steps
     k_total, k_each = (ctx.kernel_times() if not args.graph else (None, []))
     if args.staged and k_each:  # the two stage kernels of a step, summed
@@ -467,10 +497,13 @@ def run(args, wl, dev, field, dc, start, pool, sb, sc, mixed, plain, label):
         from paper_2604_11008_amd import profsum
         wg, items = ctx.get_tuning()[:2]
         tf = lambda b: "true" if b else "false"  # noqa: E731
+        # the last template argument: field arrangement (0 split, 1 MAC, 2 interleaved)
+        arr = 1 if args.stagger else (2 if field.interleaved else 0)
         variant = (f"k_step<{wg}, {items}, {'float' if mixed else 'double'}, "
-                   f"{tf(wl.halo)}, {tf(args.drag == 'nonlinear')}, {tf(args.stagger)}>")
+                   f"{tf(wl.halo)}, {tf(args.drag == 'nonlinear')}, {arr}>")
+        lay = "_interleaved" if field.interleaved else ""
         tpath = args.traffic or os.path.join(ROOT, "profiles",
-                                             f"k_step_{args.config}_{mode}_traffic.json")
+                                             f"k_step_{args.config}_{mode}{lay}_traffic.json")
         traffic = None
         # the record was taken on the canonical start order of this workload
         if os.path.exists(tpath) and json.load(open(tpath)).get("kernel") == variant \
@@ -658,9 +691,20 @@ def main():
     log(f"{args.config}: {npart} particles, field {wl.n}^3 halo={wl.halo}, "
         f"{dc.nsub} subdomains, dt={wl.dt:.4g}, gen {t_gen:.1f}s, runs {modes}")
 
+    layout = args.layout
+    if layout == "auto":
+        layout = "both" if args.config == "C5" and not args.stagger else "split"
+    if layout != "split" and (args.stagger or args.staged):
+        raise SystemExit("the interleaved layout is for collocated fields and the "
+                         "once-per-step migration")
     plain_on = args.plain == "on" or (args.plain == "auto" and precision == "both")
     args.first_mode = modes[0]
-    results = {}
+    # the interleaved runs from the same start: timed steps only (no samples,
+    # graph replay or plain path), in the split run's launch shape
+    ilv_args = argparse.Namespace(**vars(args))
+    ilv_args.no_cpu = ilv_args.no_graph_replay = True
+    ilv_args.cpu_delegated = ilv_args.migration_only = ilv_args.plain_per_sub = False
+    results, ilv_results = {}, {}
     for mode in modes:
         if mode == "f64":
             field, start = field64, start64
@@ -669,9 +713,26 @@ def main():
                                    device=dev, stagger=args.stagger)
             start = (start64[0], start64[1].float(), start64[2].float(), start64[3],
                      start64[4])
-        results[mode] = run(args, wl, dev, field, dc, start, pool, sb, sc, mode == "mixed",
-                            plain_on and mode == "f64", mode)
-        del field, start
+        if layout != "interleaved":
+            results[mode] = run(args, wl, dev, field, dc, start, pool, sb, sc,
+                                mode == "mixed", plain_on and mode == "f64", mode)
+        if layout != "split":
+            # a change of storage only: component c of stored node m at 3m + c
+            fi = pm.DeviceField(torch.stack(field.u, dim=1), wl.n, wl.halo, wl.L, device=dev,
+                                interleaved=True)
+            if mode != "f64":
+                del field
+            torch.cuda.empty_cache()
+            if layout == "interleaved":
+                results[mode] = run(args, wl, dev, fi, dc, start, pool, sb, sc,
+                                    mode == "mixed", plain_on and mode == "f64", mode)
+            else:
+                ilv_args.tune = ",".join(str(v) for v in results[mode]["tuning"])
+                ilv_results[mode] = run(ilv_args, wl, dev, fi, dc, start, pool, sb, sc,
+                                        mode == "mixed", False, f"{mode} interleaved")
+            del fi
+        field = None
+        del start
         torch.cuda.empty_cache()
     head = results[modes[0]]
     del start64, pa, field64
@@ -679,7 +740,7 @@ def main():
 
     # a plain device copy of 1 GiB: the copy rate the kernel is also compared with
     cms, copy_gbps = copy_rate(dev)
-    for r in results.values():
+    for r in list(results.values()) + list(ilv_results.values()):
         roof = r["roofline"]
         if roof is not None:
             roof["frac_of_copy"] = round(roof["achieved"] / copy_gbps, 4)
@@ -740,7 +801,7 @@ def main():
         out = {k: r[k] for k in keep if k in r}
         out["hbm_GBps_algorithmic"] = round(r["alg"]["step"] / (r["ms_per_step"] * 1e-3)
                                             / 1e9, 1)
-        if r["mode"] in errors:
+        if r["mode"] in errors and r is results.get(r["mode"]):
             out["error_vs_fp64_oracle"] = errors[r["mode"]]
         return out
 
@@ -758,6 +819,7 @@ def main():
                    (f", {args.order} particle order" if args.order != "canonical" else "") +
                    (f", re-sorted by cell every {args.resort} steps" if args.resort else ""),
                    "particles": npart, "grid": wl.n, "halo": wl.halo,
+                   "field_layout": "interleaved" if layout == "interleaved" else "split",
                    "subdomains": list(wl.p), "graph": bool(args.graph),
                    "tuning": head["tuning"],
                    "runs": {m: ("float64 field, velocities and tau" if m == "f64" else
@@ -785,6 +847,22 @@ def main():
         if "plain_ms_per_step_incl_copy" in head:
             line["mixed"]["speedup_vs_plain_f64"] = round(
                 head["plain_ms_per_step_incl_copy"] / mx["ms_per_step"], 3)
+    if ilv_results:
+        line["interleaved"] = {}
+        for m, r in ilv_results.items():
+            e = summary(r)
+            e["speedup_vs_split"] = round(results[m]["ms_per_step"] / r["ms_per_step"], 3)
+            e["bitwise_equal_to_split"] = r["state_digest"] == results[m]["state_digest"]
+            line["interleaved"][m] = e
+        line["interleaved"]["what"] = (
+            "the same steps from the same start state with the field stored node-"
+            "interleaved (component c of node m at 3m + c), as a solver that can store "
+            "it would hand it over; the library never converts a field")
+        if not all(e["bitwise_equal_to_split"] for k, e in line["interleaved"].items()
+                   if k != "what"):
+            print(json.dumps(line), flush=True)
+            raise SystemExit("interleaved layout: final state differs from the split run's")
+    line["state_digest"] = head["state_digest"]
     print(json.dumps(line), flush=True)
 
 

@@ -156,12 +156,19 @@ pm_status conv_field(const pm_field *f, pm::DField &d, bool &mixed)
         return arg_error("field.dtype must be PM_F64 or PM_F32");
     if (f->stagger != 0 && f->stagger != 1)
         return arg_error("field.stagger must be 0 or 1");
+    if (f->layout != PM_LAYOUT_SPLIT && f->layout != PM_LAYOUT_INTERLEAVED)
+        return arg_error("field.layout must be PM_LAYOUT_SPLIT or PM_LAYOUT_INTERLEAVED");
+    const bool ilv = f->layout == PM_LAYOUT_INTERLEAVED;
+    if (ilv && f->stagger)
+        return arg_error("an interleaved field must be collocated (stagger 0)");
+    if (ilv && (f->u[1] || f->u[2]))
+        return arg_error("field.u[1] and field.u[2] must be NULL for an interleaved field");
     for (int a = 0; a < 3; ++a) {
         if (f->n[a] < 2 || f->n[a] > (1 << 20))
             return arg_error("field.n[%d] = %d out of range", a, f->n[a]);
         if (!(f->L[a] > 0.0) || !std::isfinite(f->L[a]))
             return arg_error("field.L[%d] must be positive and finite", a);
-        if (!f->u[a])
+        if (!f->u[a] && (a == 0 || !ilv))
             return arg_error("field.u[%d] is NULL", a);
     }
     const int64_t sx = f->n[0] + 2 * f->halo, sy = f->n[1] + 2 * f->halo,
@@ -175,6 +182,7 @@ pm_status conv_field(const pm_field *f, pm::DField &d, bool &mixed)
     }
     d.halo = f->halo;
     d.stagger = f->stagger;
+    d.layout = f->layout;
     d.sx = sx;
     d.sxy = sx * sy;
     mixed = f->dtype == PM_F32;
@@ -348,7 +356,7 @@ pm::Shape shape_for(pm_ctx *ctx, bool mixed, bool halo, bool nonlinear, bool sta
 }
 
 int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed, bool halo, bool nonlinear,
-                    bool stagger)
+                    int arr)
 {
     // An explicit figure may exceed the runtime's occupancy estimate: workgroups
     // that do not fit start as others retire.  Tiles are claimed by ticket when
@@ -357,7 +365,7 @@ int persistent_grid(pm_ctx *ctx, pm::Shape sh, bool mixed, bool halo, bool nonli
     // group has running workgroups, since workgroups start in index order.
     const int per = ctx->blocks_per_cu > 0 ? ctx->blocks_per_cu
                                            : pm::step_occupancy(sh, mixed, halo, nonlinear,
-                                                                stagger);
+                                                                arr);
     return std::max(1, ctx->cus * per);
 }
 
@@ -387,7 +395,7 @@ pm_status queue_step(pm_ctx *ctx, pm::KArgs &k, bool mixed, hipStream_t st, bool
     if (timed)
         PM_HIP(hipEventRecord(ctx->events[2 * ctx->tcount], st), "event record");
     const int grid =
-        persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
+        persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0, pm::field_arr(k.f));
     set_groups(ctx, k, grid);
     PM_HIP(pm::launch_step(k, sh, mixed, grid, st), "fused step launch");
     if (timed) {
@@ -585,7 +593,8 @@ pm_status pm_interp_advance(pm_ctx *ctx, const pm_field *field, pm_particles *in
     const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
     k.tile = sh.wg * sh.items;
     PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn, st), "prep launch");
-    const int grid = persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0);
+    const int grid =
+        persistent_grid(ctx, sh, mixed, k.f.halo != 0, k.drag != 0, pm::field_arr(k.f));
     set_groups(ctx, k, grid);
     PM_HIP(pm::launch_advance(k, sh, mixed, grid, st),
            "advance launch");
@@ -628,7 +637,7 @@ pm_status pm_classify_scan_pack(pm_ctx *ctx, const pm_decomp *decomp, const pm_p
                                pm::kPrepZeroCounts | pm::kPrepCheckIn | pm::kPrepCheckSend,
                            st),
            "prep launch");
-    const int grid = persistent_grid(ctx, sh, mixed, false, false, false);
+    const int grid = persistent_grid(ctx, sh, mixed, false, false, pm::kFieldSplit);
     set_groups(ctx, k, grid);
     PM_HIP(pm::launch_classify(k, sh, mixed, grid, st),
            "classify launch");
@@ -673,7 +682,7 @@ pm_status pm_compact_append(pm_ctx *ctx, const pm_decomp *decomp, const pm_parti
                                   pm::kPrepCheckSend,
                            st),
            "prep launch");
-    PM_HIP(pm::launch_compact(k, sh, mixed, persistent_grid(ctx, sh, mixed, false, false, false), st),
+    PM_HIP(pm::launch_compact(k, sh, mixed, persistent_grid(ctx, sh, mixed, false, false, pm::kFieldSplit), st),
            "compact launch");
     const int grid = std::min(4096, sub_count * k.cpt);
     PM_HIP(pm::launch_append(k, mixed, std::max(1, grid), st), "append launch");
@@ -750,8 +759,9 @@ pm_status pm_step_staged(pm_ctx *ctx, const pm_field *field, const pm_decomp *de
     pm_status s = step_args(ctx, field, decomp, in, out, send, params, k, mixed);
     if (s)
         return s;
-    if (field->stagger)
-        return arg_error("per-stage migration takes a collocated field");
+    if (field->stagger || field->layout)
+        return arg_error("per-stage migration takes a collocated field stored as one array "
+                         "per component");
     pm::DPool dmid, dms;
     std::memset(&dmid, 0, sizeof dmid);  // the bytes are part of a graph key
     std::memset(&dms, 0, sizeof dms);
@@ -1056,9 +1066,11 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
     // precision, drag law, decomposition, pool extent, tile order
     char key[320];
     snprintf(key, sizeof key,
-             "n=%d,%d,%d halo=%d dtype=%d stagger=%d drag=%d nsub=%d extent=%lld xcd=%d",
+             "n=%d,%d,%d halo=%d dtype=%d stagger=%d layout=%d drag=%d nsub=%d extent=%lld "
+             "xcd=%d",
              field->n[0], field->n[1], field->n[2], field->halo, field->dtype, field->stagger,
-             params->drag, k.dc.nsub, (long long)ctx->ws.pool_extent, ctx->xcd_block);
+             field->layout, params->drag, k.dc.nsub, (long long)ctx->ws.pool_extent,
+             ctx->xcd_block);
     if (cache_path) {
         if (FILE *fp = fopen(cache_path, "r")) {
             char line[512];

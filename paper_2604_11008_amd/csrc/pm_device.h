@@ -164,11 +164,29 @@ __device__ __forceinline__ void load_pair(const FT *p, FT &lo, FT &hi)
     hi = q.b;
 }
 
+// Six consecutive values: the three components of two x-adjacent nodes of
+// a node-interleaved field (48 bytes for double, 24 for float), in as few
+// vector loads as the size allows; the address is only FT-aligned.
+template <typename FT>
+__device__ __forceinline__ void load_six(const FT *p, FT w[6])
+{
+    struct Six {
+        FT w[6];
+    } q;
+    __builtin_memcpy(&q, p, sizeof q);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        w[i] = q.w[i];
+}
+
 // The 24 node values of a stencil: v[c][2*r + x] for component c, row r
-// (y and z corner: 00, 10, 01, 11) and x corner x.  Each row's x pair is one
-// load; where a periodic field wraps (x corner n-1, then 0) the pair starts
-// one node earlier and the node at 0 is loaded on its own (n >= 2).
-template <typename FT, bool HALO>
+// (y and z corner: 00, 10, 01, 11) and x corner x.  Split arrays: each
+// row's x pair of a component is one load.  Interleaved (ILV, the three
+// components of a node next to each other): each row's two nodes are one
+// run of six values.  Where a periodic field wraps (x corner n-1, then 0)
+// the run starts one node earlier and the node at 0 is loaded on its own
+// (n >= 2).
+template <typename FT, bool HALO, bool ILV>
 __device__ __forceinline__ void stencil_load(const DField &f, const int c0[3], FT v[3][8])
 {
     const int cx1 = next_corner<HALO>(f, 0, c0[0]);
@@ -180,6 +198,29 @@ __device__ __forceinline__ void stencil_load(const DField &f, const int c0[3], F
                           f.sx * (int64_t)cy1 + f.sxy * (int64_t)cz1};
     const bool wrap = !HALO && cx1 != c0[0] + 1;
     const int xa = wrap ? c0[0] - 1 : c0[0];
+    if constexpr (ILV) {
+        const FT *u = (const FT *)f.u[0];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            FT w[6];
+            load_six<FT>(u + 3 * (r[k] + xa), w);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                v[c][2 * k] = w[c];
+                v[c][2 * k + 1] = w[3 + c];
+            }
+        }
+        if (wrap) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    v[c][2 * k] = v[c][2 * k + 1];
+                    v[c][2 * k + 1] = u[3 * (r[k] + cx1) + c];
+                }
+        }
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const FT *u = (const FT *)f.u[c];
@@ -270,12 +311,12 @@ __device__ __forceinline__ FT comp_eval(const FT v[8], const FT fr[3])
     return lerp(lerp(l00, l10, fr[1]), lerp(l01, l11, fr[1]), fr[2]);
 }
 
-// U(X) by trilinear interpolation (Sect. 2.2); STAG: from a MAC field.
-template <typename FT, bool HALO, bool STAG = false>
+// U(X) by trilinear interpolation (Sect. 2.2) from a field of arrangement FA.
+template <typename FT, bool HALO, int FA = kFieldSplit>
 __device__ __forceinline__ void interp(const DField &f, const double X[3], FT U[3],
                                        uint32_t &fl)
 {
-    if (STAG) {
+    if constexpr (FA == kFieldMac) {
         int c0[3][3];
         FT fr[3][3], v[3][8];
         mac_index<FT, HALO>(f, X, c0, fr, fl);
@@ -290,7 +331,7 @@ __device__ __forceinline__ void interp(const DField &f, const double X[3], FT U[
     int c0[3];
     FT fr[3], v[3][8];
     stencil_index<FT, HALO>(f, X, c0, fr, fl);
-    stencil_load<FT, HALO>(f, c0, v);
+    stencil_load<FT, HALO, FA == kFieldIlv>(f, c0, v);
     stencil_eval<FT>(v, fr, U);
 }
 
@@ -329,7 +370,7 @@ __device__ __forceinline__ FT drag_factor(FT kappa, FT tau, const FT s[3])
 // depend on the stage-1 interpolation, so both stencils are located first
 // and fetched in one round trip; most stage-2 stencils fall in the stage-1
 // cell and are not fetched again.  NL: the nonlinear drag factor, else f = 1.
-template <typename FT, bool HALO, bool NL, bool STAG>
+template <typename FT, bool HALO, bool NL, int FA>
 __device__ __forceinline__ void advance_one(const KArgs &a, double X[3], FT V[3], FT tau,
                                             uint32_t &fl)
 {
@@ -339,7 +380,7 @@ __device__ __forceinline__ void advance_one(const KArgs &a, double X[3], FT V[3]
     for (int c = 0; c < 3; ++c)
         Xs[c] = fma(a.dt, (double)V[c], X[c]);
     FT U1[3], U2[3];
-    if (STAG) {
+    if constexpr (FA == kFieldMac) {
         int c1[3][3], c2[3][3];
         FT fr1[3][3], fr2[3][3], S1[3][8], S2[3][8];
         mac_index<FT, HALO>(a.f, X, c1, fr1, fl);
@@ -365,9 +406,9 @@ __device__ __forceinline__ void advance_one(const KArgs &a, double X[3], FT V[3]
         stencil_index<FT, HALO>(a.f, X, c1, fr1, fl);
         stencil_index<FT, HALO>(a.f, Xs, c2, fr2, fl);
         const bool moved = c2[0] != c1[0] || c2[1] != c1[1] || c2[2] != c1[2];
-        stencil_load<FT, HALO>(a.f, c1, S1);
+        stencil_load<FT, HALO, FA == kFieldIlv>(a.f, c1, S1);
         if (moved)
-            stencil_load<FT, HALO>(a.f, c2, S2);
+            stencil_load<FT, HALO, FA == kFieldIlv>(a.f, c2, S2);
         stencil_eval<FT>(S1, fr1, U1);
         if (moved)
             stencil_eval<FT>(S2, fr2, U2);
@@ -1002,7 +1043,7 @@ __device__ __forceinline__ void scatter_stash(const KArgs &a, const TileLds<WG, 
 // A tile's aggregate never waits on anything, so every walk ends.
 // At least two waves per SIMD (one with 8 records per thread, which cannot
 // fit two): the compiler spills a few registers rather than halve occupancy.
-template <int WG, int ITEMS, typename FT, bool HALO, bool NL, bool STAG>
+template <int WG, int ITEMS, typename FT, bool HALO, bool NL, int FA>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ? 1 : 2))) void k_step(const KArgs a)
 {
     constexpr int NW = WG / 64;
@@ -1052,7 +1093,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ?
         for (int k = 0; k < ITEMS; ++k) {
             d[k] = 0xff;
             if (k * WG + tid < nitems) {
-                advance_one<FT, HALO, NL, STAG>(a, X[k], V[k], tau[k], fl);
+                advance_one<FT, HALO, NL, FA>(a, X[k], V[k], tau[k], fl);
                 d[k] = classify(a.dc, own, X[k], fl);
             }
         }
@@ -1107,7 +1148,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ?
 }
 
 // Plain path, steps 1-2: in-place advance of the range's records.
-template <int WG, int ITEMS, typename FT, bool HALO, bool NL, bool STAG>
+template <int WG, int ITEMS, typename FT, bool HALO, bool NL, int FA>
 __global__ __launch_bounds__(WG) void k_advance(const KArgs a)
 {
     __shared__ TileHead H;
@@ -1141,7 +1182,7 @@ __global__ __launch_bounds__(WG) void k_advance(const KArgs a)
         for (int k = 0; k < ITEMS; ++k) {
             const int i = k * WG + tid;
             if (i < nitems) {
-                advance_one<FT, HALO, NL, STAG>(a, X[k], V[k], tau[k], fl);
+                advance_one<FT, HALO, NL, FA>(a, X[k], V[k], tau[k], fl);
                 const int64_t p = first + i;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -1514,7 +1555,7 @@ __global__ __launch_bounds__(256) void k_append(const KArgs a)
         flag_or(hdr, fl);
 }
 
-template <typename FT, bool HALO, bool STAG>
+template <typename FT, bool HALO, int FA>
 __global__ __launch_bounds__(256) void k_interp(const KArgs a, int64_t n, const double *x,
                                                 const double *y, const double *z, FT *ux,
                                                 FT *uy, FT *uz)
@@ -1524,7 +1565,7 @@ __global__ __launch_bounds__(256) void k_interp(const KArgs a, int64_t n, const 
          i += (int64_t)gridDim.x * 256) {
         const double X[3] = {x[i], y[i], z[i]};
         FT U[3];
-        interp<FT, HALO, STAG>(a.f, X, U, fl);
+        interp<FT, HALO, FA>(a.f, X, U, fl);
         ux[i] = U[0];
         uy[i] = U[1];
         uz[i] = U[2];
@@ -1917,44 +1958,44 @@ __global__ __launch_bounds__(WG) void k_stage(const KArgs a)
 // variants; Kern<W, I>::step/advance pick the one for the launch.
 template <int W, int I>
 struct Kern {
-    template <typename FT, bool H, bool NL, bool SG>
+    template <typename FT, bool H, bool NL, int FA>
     static hipError_t step_t(const KArgs &a, int grid, hipStream_t st)
     {
-        hipLaunchKernelGGL((k_step<W, I, FT, H, NL, SG>), dim3(grid), dim3(W), 0, st, a);
+        hipLaunchKernelGGL((k_step<W, I, FT, H, NL, FA>), dim3(grid), dim3(W), 0, st, a);
         return hipGetLastError();
     }
-    template <typename FT, bool H, bool NL, bool SG>
+    template <typename FT, bool H, bool NL, int FA>
     static hipError_t advance_t(const KArgs &a, int grid, hipStream_t st)
     {
-        hipLaunchKernelGGL((k_advance<W, I, FT, H, NL, SG>), dim3(grid), dim3(W), 0, st, a);
+        hipLaunchKernelGGL((k_advance<W, I, FT, H, NL, FA>), dim3(grid), dim3(W), 0, st, a);
         return hipGetLastError();
     }
-    template <typename FT, bool H, bool NL, bool SG>
+    template <typename FT, bool H, bool NL, int FA>
     static int occupancy_t()
     {
         int nb = 1;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, FT, H, NL, SG>),
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_step<W, I, FT, H, NL, FA>),
                                                            W, 0);
         return nb;
     }
-    // the halo x drag-law variants of one element type and field arrangement
-    template <typename FT, bool SG>
+    // the halo x drag-law variants of one element type and field arrangement FA
+    template <typename FT, int FA>
     static hipError_t step_ft(const KArgs &a, int grid, hipStream_t st)
     {
         const bool h = a.f.halo != 0, nl = a.drag != 0;
-        return h ? (nl ? step_t<FT, true, true, SG>(a, grid, st)
-                       : step_t<FT, true, false, SG>(a, grid, st))
-                 : (nl ? step_t<FT, false, true, SG>(a, grid, st)
-                       : step_t<FT, false, false, SG>(a, grid, st));
+        return h ? (nl ? step_t<FT, true, true, FA>(a, grid, st)
+                       : step_t<FT, true, false, FA>(a, grid, st))
+                 : (nl ? step_t<FT, false, true, FA>(a, grid, st)
+                       : step_t<FT, false, false, FA>(a, grid, st));
     }
-    template <typename FT, bool SG>
+    template <typename FT, int FA>
     static hipError_t advance_ft(const KArgs &a, int grid, hipStream_t st)
     {
         const bool h = a.f.halo != 0, nl = a.drag != 0;
-        return h ? (nl ? advance_t<FT, true, true, SG>(a, grid, st)
-                       : advance_t<FT, true, false, SG>(a, grid, st))
-                 : (nl ? advance_t<FT, false, true, SG>(a, grid, st)
-                       : advance_t<FT, false, false, SG>(a, grid, st));
+        return h ? (nl ? advance_t<FT, true, true, FA>(a, grid, st)
+                       : advance_t<FT, true, false, FA>(a, grid, st))
+                 : (nl ? advance_t<FT, false, true, FA>(a, grid, st)
+                       : advance_t<FT, false, false, FA>(a, grid, st));
     }
     template <typename FT, bool H, bool NL, int STG>
     static hipError_t stage_t(const KArgs &a, int grid, hipStream_t st)
@@ -1987,11 +2028,11 @@ struct Kern {
                  : (nl ? stage_occ_t<FT, false, true, STG>()
                        : stage_occ_t<FT, false, false, STG>());
     }
-    template <typename FT, bool SG>
+    template <typename FT, int FA>
     static int occupancy_ft(bool h, bool nl)
     {
-        return h ? (nl ? occupancy_t<FT, true, true, SG>() : occupancy_t<FT, true, false, SG>())
-                 : (nl ? occupancy_t<FT, false, true, SG>() : occupancy_t<FT, false, false, SG>());
+        return h ? (nl ? occupancy_t<FT, true, true, FA>() : occupancy_t<FT, true, false, FA>())
+                 : (nl ? occupancy_t<FT, false, true, FA>() : occupancy_t<FT, false, false, FA>());
     }
 };
 

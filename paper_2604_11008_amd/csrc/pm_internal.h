@@ -28,14 +28,25 @@ enum { kHdrFlags = 0, kHdrTicket = 1, kHdrTiles = 2, kHdrGroupTicket = 32, kHdrW
 enum { kMaxGroups = 8 };
 
 struct DField {
-    const void *u[3];
+    const void *u[3];  // interleaved: u[0] only
     int32_t n[3];
     int32_t halo;
     int32_t stagger; // 0 collocated, 1 MAC (component c face-centred along axis c)
+    int32_t layout;  // 0 one array per component, 1 node-interleaved (collocated only)
     double r[3];     // n / L per axis
     int64_t sx;      // stored row length (n0 + 2 halo)
     int64_t sxy;     // stored plane size
 };
+
+// Field arrangements of the interpolating kernels (their template parameter
+// FA): collocated with one array per component, MAC, collocated with the
+// three components of a node interleaved.
+enum { kFieldSplit = 0, kFieldMac = 1, kFieldIlv = 2 };
+
+inline int field_arr(const DField &f)
+{
+    return f.stagger ? kFieldMac : (f.layout ? kFieldIlv : kFieldSplit);
+}
 
 struct DDecomp {
     int32_t p[3];
@@ -150,22 +161,30 @@ hipError_t launch_fill(uint64_t *p, int64_t words, hipStream_t st);
 // hdr's flag word into *dst (dst may be NULL), then cleared.
 hipError_t launch_flags_move(uint32_t *hdr, uint32_t *dst, hipStream_t st);
 
-// Workgroups per CU that fit for a launch shape of the fused kernel.
-int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, bool stagger);
+// Workgroups per CU that fit for a launch shape of the fused kernel on a
+// field of arrangement `arr` (kField*).
+int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, int arr);
 // per element type (pm_step_f64.hip, pm_step_f32.hip; the MAC variants in
-// pm_mac_f64.hip, pm_mac_f32.hip)
+// pm_mac_f64.hip, pm_mac_f32.hip, the interleaved ones in pm_ilv_f64.hip,
+// pm_ilv_f32.hip)
 hipError_t launch_step_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
 hipError_t launch_step_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
 hipError_t launch_advance_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
 hipError_t launch_advance_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
-int step_occupancy_f64(Shape sh, bool halo, bool nonlinear, bool stagger);
-int step_occupancy_f32(Shape sh, bool halo, bool nonlinear, bool stagger);
+int step_occupancy_f64(Shape sh, bool halo, bool nonlinear, int arr);
+int step_occupancy_f32(Shape sh, bool halo, bool nonlinear, int arr);
 hipError_t launch_step_mac_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
 hipError_t launch_step_mac_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
 hipError_t launch_advance_mac_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
 hipError_t launch_advance_mac_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
 int step_occupancy_mac_f64(Shape sh, bool halo, bool nonlinear);
 int step_occupancy_mac_f32(Shape sh, bool halo, bool nonlinear);
+hipError_t launch_step_ilv_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
+hipError_t launch_step_ilv_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
+hipError_t launch_advance_ilv_f64(const KArgs &a, Shape sh, int grid, hipStream_t st);
+hipError_t launch_advance_ilv_f32(const KArgs &a, Shape sh, int grid, hipStream_t st);
+int step_occupancy_ilv_f64(Shape sh, bool halo, bool nonlinear);
+int step_occupancy_ilv_f32(Shape sh, bool halo, bool nonlinear);
 // per-stage migration: the fused kernel of stage 1 or 2 (pm_staged_f64.hip,
 // pm_staged_f32.hip)
 bool stage_shape_supported(Shape sh);

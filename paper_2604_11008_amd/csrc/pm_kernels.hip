@@ -99,24 +99,35 @@ hipError_t launch_route(const KArgs &a, bool mixed, bool append, hipStream_t st,
     return hipGetLastError();
 }
 
-template <typename FT, bool H, bool SG>
+template <typename FT, bool H, int FA>
 hipError_t interp_t(const KArgs &a, int grid, int64_t n, const double *x, const double *y,
                     const double *z, void *ux, void *uy, void *uz, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_interp<FT, H, SG>), dim3(grid), dim3(256), 0, st, a, n, x, y, z,
+    hipLaunchKernelGGL((k_interp<FT, H, FA>), dim3(grid), dim3(256), 0, st, a, n, x, y, z,
                        (FT *)ux, (FT *)uy, (FT *)uz);
     return hipGetLastError();
+}
+
+template <typename FT, bool H>
+hipError_t interp_h(const KArgs &a, int grid, int64_t n, const double *x, const double *y,
+                    const double *z, void *ux, void *uy, void *uz, hipStream_t st)
+{
+    switch (field_arr(a.f)) {
+    case kFieldMac:
+        return interp_t<FT, H, kFieldMac>(a, grid, n, x, y, z, ux, uy, uz, st);
+    case kFieldIlv:
+        return interp_t<FT, H, kFieldIlv>(a, grid, n, x, y, z, ux, uy, uz, st);
+    default:
+        return interp_t<FT, H, kFieldSplit>(a, grid, n, x, y, z, ux, uy, uz, st);
+    }
 }
 
 template <typename FT>
 hipError_t interp_ft(const KArgs &a, int grid, int64_t n, const double *x, const double *y,
                      const double *z, void *ux, void *uy, void *uz, hipStream_t st)
 {
-    const bool h = a.f.halo != 0, sg = a.f.stagger != 0;
-    return h ? (sg ? interp_t<FT, true, true>(a, grid, n, x, y, z, ux, uy, uz, st)
-                   : interp_t<FT, true, false>(a, grid, n, x, y, z, ux, uy, uz, st))
-             : (sg ? interp_t<FT, false, true>(a, grid, n, x, y, z, ux, uy, uz, st)
-                   : interp_t<FT, false, false>(a, grid, n, x, y, z, ux, uy, uz, st));
+    return a.f.halo != 0 ? interp_h<FT, true>(a, grid, n, x, y, z, ux, uy, uz, st)
+                         : interp_h<FT, false>(a, grid, n, x, y, z, ux, uy, uz, st);
 }
 
 hipError_t launch_interp(const KArgs &a, bool mixed, int64_t n, const double *x,
@@ -191,10 +202,10 @@ int stage_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, int stage)
     return nb < 1 ? 1 : nb;
 }
 
-int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, bool stagger)
+int step_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, int arr)
 {
-    const int nb = mixed ? step_occupancy_f32(sh, halo, nonlinear, stagger)
-                         : step_occupancy_f64(sh, halo, nonlinear, stagger);
+    const int nb = mixed ? step_occupancy_f32(sh, halo, nonlinear, arr)
+                         : step_occupancy_f64(sh, halo, nonlinear, arr);
     return nb < 1 ? 1 : nb;
 }
 

@@ -6,7 +6,7 @@ namespace pm {
 
 #define PM_STEP_CASE(W, I)                                                             \
     if (sh.wg == W && sh.items == I)                                                   \
-        return Kern<W, I>::step_ft<double, true>(a, grid, st);
+        return Kern<W, I>::step_ft<double, kFieldMac>(a, grid, st);
 
 hipError_t launch_step_mac_f64(const KArgs &a, Shape sh, int grid, hipStream_t st)
 {
@@ -16,7 +16,7 @@ hipError_t launch_step_mac_f64(const KArgs &a, Shape sh, int grid, hipStream_t s
 
 #define PM_ADV_CASE(W, I)                                                              \
     if (sh.wg == W && sh.items == I)                                                   \
-        return Kern<W, I>::advance_ft<double, true>(a, grid, st);
+        return Kern<W, I>::advance_ft<double, kFieldMac>(a, grid, st);
 
 hipError_t launch_advance_mac_f64(const KArgs &a, Shape sh, int grid, hipStream_t st)
 {
@@ -26,7 +26,7 @@ hipError_t launch_advance_mac_f64(const KArgs &a, Shape sh, int grid, hipStream_
 
 #define PM_OCC_CASE(W, I)                                                              \
     if (sh.wg == W && sh.items == I)                                                   \
-        return Kern<W, I>::occupancy_ft<double, true>(halo, nonlinear);
+        return Kern<W, I>::occupancy_ft<double, kFieldMac>(halo, nonlinear);
 
 int step_occupancy_mac_f64(Shape sh, bool halo, bool nonlinear)
 {

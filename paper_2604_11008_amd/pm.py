@@ -17,6 +17,7 @@ import torch
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpm.so")
 
 F64, F32 = 0, 1
+LAYOUT_SPLIT, LAYOUT_INTERLEAVED = 0, 1
 STAY = 13
 SEND_OVERFLOW, DEST_OVERFLOW, SKIP, NONFINITE, HALO, LAYOUT = 1, 2, 4, 8, 16, 32
 FLAG_NAMES = {SEND_OVERFLOW: "SEND_OVERFLOW", DEST_OVERFLOW: "DEST_OVERFLOW", SKIP: "SKIP",
@@ -32,7 +33,8 @@ class PMError(RuntimeError):
 
 class _Field(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("halo", C.c_int32), ("L", C.c_double * 3),
-                ("dtype", C.c_int32), ("stagger", C.c_int32), ("u", C.c_void_p * 3)]
+                ("dtype", C.c_int32), ("stagger", C.c_int32), ("u", C.c_void_p * 3),
+                ("layout", C.c_int32)]
 
 
 class _Decomp(C.Structure):
@@ -148,13 +150,20 @@ def _rows(t: torch.Tensor):
 # --- device-side objects -------------------------------------------------------------
 
 class DeviceField:
-    """Velocity field on the device: three flat tensors (float64 or float32);
-    stagger=True: MAC arrangement (component c on the faces normal to axis c)."""
+    """Velocity field on the device (float64 or float32).  Split layout:
+    `u` is three flat tensors, one per component; stagger=True: MAC
+    arrangement (component c on the faces normal to axis c).  Interleaved
+    layout (interleaved=True, collocated only): `u` is one tensor of three
+    values per stored node, component fastest (shape (nodes, 3) or flat)."""
 
-    def __init__(self, u, n, halo, L, device="cuda", stagger=False):
-        self.u = [torch.as_tensor(np.ascontiguousarray(c).reshape(-1)).to(device)
-                  if not isinstance(c, torch.Tensor) else c.reshape(-1).contiguous()
-                  for c in u]
+    def __init__(self, u, n, halo, L, device="cuda", stagger=False, interleaved=False):
+        def flat(c):
+            if isinstance(c, torch.Tensor):
+                return c.reshape(-1).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(c).reshape(-1)).to(device)
+
+        self.interleaved = bool(interleaved)
+        self.u = [flat(u)] if self.interleaved else [flat(c) for c in u]
         dt = self.u[0].dtype
         if dt not in (torch.float64, torch.float32) or any(c.dtype != dt for c in self.u):
             raise PMError("field components must all be float64 or all float32")
@@ -162,12 +171,22 @@ class DeviceField:
         self.halo = int(halo)
         self.L = (L, L, L) if np.isscalar(L) else tuple(L)
         st = [k + 2 * self.halo for k in self.n]
-        if any(c.numel() != st[0] * st[1] * st[2] for c in self.u):
-            raise PMError("field size does not match n and halo")
+        nodes = st[0] * st[1] * st[2]
+        if self.interleaved:
+            if stagger:
+                raise PMError("an interleaved field must be collocated")
+            if self.u[0].numel() != 3 * nodes:
+                raise PMError("interleaved field size does not match n and halo")
+            ptrs = [_p(self.u[0]), None, None]
+        else:
+            if len(self.u) != 3 or any(c.numel() != nodes for c in self.u):
+                raise PMError("field size does not match n and halo")
+            ptrs = [_p(c) for c in self.u]
         self.dtype = F64 if dt == torch.float64 else F32
         self.stagger = int(bool(stagger))
+        self.layout = LAYOUT_INTERLEAVED if self.interleaved else LAYOUT_SPLIT
         self.c = _Field((C.c_int32 * 3)(*self.n), self.halo, (C.c_double * 3)(*self.L),
-                        self.dtype, self.stagger, (C.c_void_p * 3)(*[_p(c) for c in self.u]))
+                        self.dtype, self.stagger, (C.c_void_p * 3)(*ptrs), self.layout)
 
     @property
     def mixed(self):

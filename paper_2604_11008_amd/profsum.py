@@ -28,7 +28,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 # the kernel sources and the workload generator (the traffic depends on both)
 SOURCES = [os.path.join(PKG, "csrc", f) for f in ("pm_device.h", "pm_step_f64.hip",
                                                     "pm_step_f32.hip", "pm_mac_f64.hip",
-                                                    "pm_mac_f32.hip", "pm_staged_f64.hip",
+                                                    "pm_mac_f32.hip", "pm_ilv_f64.hip",
+                                                    "pm_ilv_f32.hip", "pm_staged_f64.hip",
                                                     "pm_staged_f32.hip", "pm_kernels.hip",
                                                     "pm_internal.h")] + \
     [os.path.join(PKG, "gen.py")]

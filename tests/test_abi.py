@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def header_layout(tmp_path):
     """sizeof and field offsets of the header's structs, from a C compiler."""
     probes = {
-        "pm_field": ["n", "halo", "L", "dtype", "stagger", "u"],
+        "pm_field": ["n", "halo", "L", "dtype", "stagger", "u", "layout"],
         "pm_decomp": ["p", "bounds"],
         "pm_particles": ["nsub", "vdtype", "base", "cap", "count", "x", "v", "tau", "id"],
         "pm_sendbufs": ["base", "cap", "count", "x", "v", "tau", "id"],
@@ -143,3 +143,26 @@ def test_noalloc_argument_errors_without_a_device():
     assert lib.pm_step_noalloc(None, None, ctypes.byref(parts), None, None, None, 100, 100,
                                ctypes.byref(one), None) == 1
     assert b"nsub" in lib.pm_last_error()
+
+
+def test_binding_marshals_an_interleaved_field():
+    """An interleaved field reaches the library as u[0] = its one array,
+    u[1] = u[2] = NULL and layout 1; sizes that do not hold three values per
+    stored node, and an interleaved MAC field, are refused (host tensors
+    stand in for device ones)."""
+    import pytest
+    import torch
+    from paper_2604_11008_amd import pm
+    n, halo = (6, 5, 4), 1
+    nodes = 8 * 7 * 6
+    w = torch.zeros((nodes, 3), dtype=torch.float64)
+    f = pm.DeviceField(w, n, halo, 1.0, device="cpu", interleaved=True)
+    assert f.c.layout == pm.LAYOUT_INTERLEAVED == 1
+    assert f.c.u[0] == w.data_ptr() and f.c.u[1] is None and f.c.u[2] is None
+    split = pm.DeviceField([torch.zeros(nodes)] * 3, n, halo, 1.0, device="cpu")
+    assert split.c.layout == pm.LAYOUT_SPLIT == 0
+    with pytest.raises(pm.PMError):
+        pm.DeviceField(torch.zeros(3 * nodes - 1, dtype=torch.float64), n, halo, 1.0,
+                       device="cpu", interleaved=True)
+    with pytest.raises(pm.PMError):
+        pm.DeviceField(w, n, halo, 1.0, device="cpu", interleaved=True, stagger=True)
