@@ -149,6 +149,8 @@ def main(argv):
             print(f"{avg:12.2f} us avg {calls:6d} calls {tot:12.1f} us total  {name[:100]}")
     elif argv[0] == "trace":
         d, n = trace_window(argv[1], argv[2], int(argv[3]), int(argv[4]))
+        if not d:
+            raise SystemExit(f"{argv[2]}: {n} dispatches, none from index {argv[3]} on")
         print(f"{argv[2]}: dispatches {argv[3]}..{int(argv[3]) + len(d) - 1} of {n}: "
               f"mean {sum(d) / len(d):.2f} us, min {min(d):.2f}, max {max(d):.2f}, "
               f"first {d[0]:.2f}, last {d[-1]:.2f}")
