@@ -694,9 +694,8 @@ def main():
     layout = args.layout
     if layout == "auto":
         layout = "both" if args.config == "C5" and not args.stagger else "split"
-    if layout != "split" and (args.stagger or args.staged):
-        raise SystemExit("the interleaved layout is for collocated fields and the "
-                         "once-per-step migration")
+    if layout != "split" and args.stagger:
+        raise SystemExit("the interleaved layout is for collocated fields")
     plain_on = args.plain == "on" or (args.plain == "auto" and precision == "both")
     args.first_mode = modes[0]
     # the interleaved runs from the same start: timed steps only (no samples,

@@ -104,8 +104,9 @@ typedef enum { PM_LAYOUT_SPLIT = 0, PM_LAYOUT_INTERLEAVED = 1 } pm_layout;
  *   node m); u[1] and u[2] must be NULL.  A stencil row then takes one run
  *   of six values instead of three pairs from three arrays, which touches
  *   about half as many cache lines for isolated particles; the results are
- *   bitwise those of the split layout.  For solvers that can store the
- *   velocity this way: the library never converts a field.
+ *   bitwise those of the split layout, through every entry point.  For
+ *   solvers that can store the velocity this way: the library never
+ *   converts a field.
  * stagger == 0: collocated, node (i,j,k) of every component at the cell
  * centre ((i+1/2)L0/n0, ...), as the paper interpolates (Sect. 2.2);
  * stagger == 1: MAC arrangement, as its fluid solver stores the velocity
@@ -389,7 +390,7 @@ pm_status pm_kernel_times(pm_ctx *ctx, int32_t *n, double *total_ms, float *ms,
  * stage 2 in the new owner (X' = X_n + dt/2 (V_n + V*), V' = V_n + dt/2 (a
  * + a(X*, V*))), classified by X' and exchanged into `out` (leavers through
  * `send`).  Each exchange is the same scan, pack, compact and append as
- * pm_step's.  Collocated split fields only; `in` is unchanged; mid must fit the
+ * pm_step's.  Collocated fields (either layout); `in` is unchanged; mid must fit the
  * context's pool extent and mid_send its send extent.  Launch shapes with
  * at most 1024 records per tile (default 256 x 2, or fewer records per
  * thread for small pools as in pm_tuning).  Replayed as one HIP

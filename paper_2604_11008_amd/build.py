@@ -14,7 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpm.so")
 SOURCES = ["pm_step_f64.hip", "pm_step_f32.hip", "pm_mac_f64.hip", "pm_mac_f32.hip",
            "pm_ilv_f64.hip", "pm_ilv_f32.hip",
-           "pm_staged_f64.hip", "pm_staged_f32.hip", "pm_kernels.hip", "pm_sort.hip",
+           "pm_staged_f64.hip", "pm_staged_f32.hip", "pm_staged_ilv_f64.hip",
+           "pm_staged_ilv_f32.hip", "pm_kernels.hip", "pm_sort.hip",
            "pm_api.hip"]
 
 HIPCC_FLAGS = [

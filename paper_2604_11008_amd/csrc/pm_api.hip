@@ -735,7 +735,8 @@ static pm_status queue_stage(pm_ctx *ctx, pm::KArgs &k, bool mixed, int stage, p
            "prep launch");
     const int per = ctx->blocks_per_cu > 0
                         ? ctx->blocks_per_cu
-                        : pm::stage_occupancy(sh, mixed, k.f.halo != 0, k.drag != 0, stage);
+                        : pm::stage_occupancy(sh, mixed, k.f.halo != 0, k.drag != 0, stage,
+                                              k.f.layout != 0);
     const int grid = std::max(1, ctx->cus * per);
     set_groups(ctx, k, grid);
     if (timed)
@@ -759,9 +760,8 @@ pm_status pm_step_staged(pm_ctx *ctx, const pm_field *field, const pm_decomp *de
     pm_status s = step_args(ctx, field, decomp, in, out, send, params, k, mixed);
     if (s)
         return s;
-    if (field->stagger || field->layout)
-        return arg_error("per-stage migration takes a collocated field stored as one array "
-                         "per component");
+    if (field->stagger)
+        return arg_error("per-stage migration takes a collocated field");
     pm::DPool dmid, dms;
     std::memset(&dmid, 0, sizeof dmid);  // the bytes are part of a graph key
     std::memset(&dms, 0, sizeof dms);

@@ -1659,13 +1659,13 @@ __global__ __launch_bounds__(64) void k_flags_move(uint32_t *hdr, uint32_t *dst)
 
 // Stage 1 of the Heun step: X* = X + dt V, V* = V + dt a, a = f (U(X) - V)/tau + g
 // (the same operations as advance_one's first stage).
-template <typename FT, bool HALO, bool NL>
+template <typename FT, bool HALO, bool NL, int FA>
 __device__ __forceinline__ void heun_stage1(const KArgs &a, const double X[3], const FT V[3],
                                             FT tau, double Xs[3], FT Vs[3], FT A1[3],
                                             uint32_t &fl)
 {
     FT U1[3], s1[3];
-    interp<FT, HALO>(a.f, X, U1, fl);
+    interp<FT, HALO, FA>(a.f, X, U1, fl);
     const FT it = (FT)1 / tau;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -1685,13 +1685,13 @@ __device__ __forceinline__ void heun_stage1(const KArgs &a, const double X[3], c
 }
 
 // Stage 2 in the new owner: X' = X + dt/2 (V + V*), V' = V + dt/2 (a + a(X*, V*)).
-template <typename FT, bool HALO, bool NL>
+template <typename FT, bool HALO, bool NL, int FA>
 __device__ __forceinline__ void heun_stage2(const KArgs &a, double X[3], FT V[3],
                                             const double Xs[3], const FT Vs[3],
                                             const FT A1[3], FT tau, uint32_t &fl)
 {
     FT U2[3], s2[3];
-    interp<FT, HALO>(a.f, Xs, U2, fl);
+    interp<FT, HALO, FA>(a.f, Xs, U2, fl);
     const FT it = (FT)1 / tau;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -1812,7 +1812,7 @@ __device__ __forceinline__ void scatter_stash_x(const KArgs &a, const TileLds<WG
 // classified by X* -> mid-step records to `out` / the staging area.
 // STAGE 2: mid-step records of `in` -> stage 2 -> classified by X' -> plain
 // records to `out` / the staging area.
-template <int WG, int ITEMS, typename FT, bool HALO, bool NL, int STAGE>
+template <int WG, int ITEMS, typename FT, bool HALO, bool NL, int STAGE, int FA>
 __global__ __launch_bounds__(WG) void k_stage(const KArgs a)
 {
     constexpr int NW = WG / 64;
@@ -1864,10 +1864,10 @@ __global__ __launch_bounds__(WG) void k_stage(const KArgs a)
             d[k] = 0xff;
             if (k * WG + tid < nitems) {
                 if (STAGE == 1) {
-                    heun_stage1<FT, HALO, NL>(a, X[k], V[k], tau[k], Xs[k], Vs[k], A[k], fl);
+                    heun_stage1<FT, HALO, NL, FA>(a, X[k], V[k], tau[k], Xs[k], Vs[k], A[k], fl);
                     d[k] = classify(a.dc, own, Xs[k], fl);
                 } else {
-                    heun_stage2<FT, HALO, NL>(a, X[k], V[k], Xs[k], Vs[k], A[k], tau[k], fl);
+                    heun_stage2<FT, HALO, NL, FA>(a, X[k], V[k], Xs[k], Vs[k], A[k], tau[k], fl);
                     d[k] = classify(a.dc, own, X[k], fl);
                 }
             }
@@ -1997,36 +1997,38 @@ struct Kern {
                  : (nl ? advance_t<FT, false, true, FA>(a, grid, st)
                        : advance_t<FT, false, false, FA>(a, grid, st));
     }
-    template <typename FT, bool H, bool NL, int STG>
+    template <typename FT, bool H, bool NL, int STG, int FA>
     static hipError_t stage_t(const KArgs &a, int grid, hipStream_t st)
     {
-        hipLaunchKernelGGL((k_stage<W, I, FT, H, NL, STG>), dim3(grid), dim3(W), 0, st, a);
+        hipLaunchKernelGGL((k_stage<W, I, FT, H, NL, STG, FA>), dim3(grid), dim3(W), 0, st, a);
         return hipGetLastError();
     }
-    template <typename FT, bool H, bool NL, int STG>
+    template <typename FT, bool H, bool NL, int STG, int FA>
     static int stage_occ_t()
     {
         int nb = 1;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (k_stage<W, I, FT, H, NL, STG>),
-                                                           W, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, (k_stage<W, I, FT, H, NL, STG, FA>), W, 0);
         return nb;
     }
-    // the halo x drag-law variants of one stage of per-stage migration
-    template <typename FT, int STG>
+    // the halo x drag-law variants of one stage of per-stage migration on a
+    // collocated field of layout FA (split or interleaved)
+    template <typename FT, int STG, int FA>
     static hipError_t stage_ft(const KArgs &a, int grid, hipStream_t st)
     {
         const bool h = a.f.halo != 0, nl = a.drag != 0;
-        return h ? (nl ? stage_t<FT, true, true, STG>(a, grid, st)
-                       : stage_t<FT, true, false, STG>(a, grid, st))
-                 : (nl ? stage_t<FT, false, true, STG>(a, grid, st)
-                       : stage_t<FT, false, false, STG>(a, grid, st));
+        return h ? (nl ? stage_t<FT, true, true, STG, FA>(a, grid, st)
+                       : stage_t<FT, true, false, STG, FA>(a, grid, st))
+                 : (nl ? stage_t<FT, false, true, STG, FA>(a, grid, st)
+                       : stage_t<FT, false, false, STG, FA>(a, grid, st));
     }
-    template <typename FT, int STG>
+    template <typename FT, int STG, int FA>
     static int stage_occ_ft(bool h, bool nl)
     {
-        return h ? (nl ? stage_occ_t<FT, true, true, STG>() : stage_occ_t<FT, true, false, STG>())
-                 : (nl ? stage_occ_t<FT, false, true, STG>()
-                       : stage_occ_t<FT, false, false, STG>());
+        return h ? (nl ? stage_occ_t<FT, true, true, STG, FA>()
+                       : stage_occ_t<FT, true, false, STG, FA>())
+                 : (nl ? stage_occ_t<FT, false, true, STG, FA>()
+                       : stage_occ_t<FT, false, false, STG, FA>());
     }
     template <typename FT, int FA>
     static int occupancy_ft(bool h, bool nl)

@@ -190,11 +190,16 @@ int step_occupancy_ilv_f32(Shape sh, bool halo, bool nonlinear);
 bool stage_shape_supported(Shape sh);
 hipError_t launch_stage(const KArgs &a, Shape sh, bool mixed, int stage, int grid,
                         hipStream_t st);
-int stage_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, int stage);
+int stage_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, int stage, bool ilv);
 hipError_t launch_stage_f64(const KArgs &a, Shape sh, int stage, int grid, hipStream_t st);
 hipError_t launch_stage_f32(const KArgs &a, Shape sh, int stage, int grid, hipStream_t st);
-int stage_occupancy_f64(Shape sh, bool halo, bool nonlinear, int stage);
-int stage_occupancy_f32(Shape sh, bool halo, bool nonlinear, int stage);
+int stage_occupancy_f64(Shape sh, bool halo, bool nonlinear, int stage, bool ilv);
+int stage_occupancy_f32(Shape sh, bool halo, bool nonlinear, int stage, bool ilv);
+// on node-interleaved fields (pm_staged_ilv_f64.hip, pm_staged_ilv_f32.hip)
+hipError_t launch_stage_ilv_f64(const KArgs &a, Shape sh, int stage, int grid, hipStream_t st);
+hipError_t launch_stage_ilv_f32(const KArgs &a, Shape sh, int stage, int grid, hipStream_t st);
+int stage_occupancy_ilv_f64(Shape sh, bool halo, bool nonlinear, int stage);
+int stage_occupancy_ilv_f32(Shape sh, bool halo, bool nonlinear, int stage);
 bool shape_supported(Shape sh);
 
 }  // namespace pm

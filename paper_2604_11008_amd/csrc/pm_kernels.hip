@@ -195,10 +195,10 @@ hipError_t launch_stage(const KArgs &a, Shape sh, bool mixed, int stage, int gri
                  : launch_stage_f64(a, sh, stage, grid, st);
 }
 
-int stage_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, int stage)
+int stage_occupancy(Shape sh, bool mixed, bool halo, bool nonlinear, int stage, bool ilv)
 {
-    const int nb = mixed ? stage_occupancy_f32(sh, halo, nonlinear, stage)
-                         : stage_occupancy_f64(sh, halo, nonlinear, stage);
+    const int nb = mixed ? stage_occupancy_f32(sh, halo, nonlinear, stage, ilv)
+                         : stage_occupancy_f64(sh, halo, nonlinear, stage, ilv);
     return nb < 1 ? 1 : nb;
 }
 

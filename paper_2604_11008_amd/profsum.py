@@ -30,7 +30,8 @@ SOURCES = [os.path.join(PKG, "csrc", f) for f in ("pm_device.h", "pm_step_f64.hi
                                                     "pm_step_f32.hip", "pm_mac_f64.hip",
                                                     "pm_mac_f32.hip", "pm_ilv_f64.hip",
                                                     "pm_ilv_f32.hip", "pm_staged_f64.hip",
-                                                    "pm_staged_f32.hip", "pm_kernels.hip",
+                                                    "pm_staged_f32.hip", "pm_staged_ilv_f64.hip",
+                                                    "pm_staged_ilv_f32.hip", "pm_kernels.hip",
                                                     "pm_internal.h")] + \
     [os.path.join(PKG, "gen.py")]
 COPY_KERNEL = "__amd_rocclr_copyBuffer"

@@ -1,7 +1,8 @@
 """GPU: a field stored node-interleaved (the three components of a node next
 to each other) gives bitwise the results of the same field stored as one
 array per component, through every entry point that interpolates (Sect.
-2.2), and so the oracle's; the layout's argument checks.
+2.2), per-stage migration included (Sect. 3.2.2), and so the oracle's; the
+layout's argument checks.
 
 The interleaved copy is made by stacking the split arrays: a change of
 storage only, no arithmetic.
@@ -147,6 +148,44 @@ def test_interleaved_step_in_the_timed_shape(mode):
         say(f"  step {k + 1}: bitwise equal")
 
 
+STAGED_CASES = [
+    ("C2", 40000, 32, None, "f64", "stokes", (256, 2)),
+    ("C2S", 60000, 32, (4, 4, 4), "f64", "nonlinear", (256, 4)),
+    ("C2S", 60000, 32, (4, 4, 4), "mixed", "stokes", (512, 2)),
+    ("C3", 50000, 32, (4, 4, 4), "mixed", "nonlinear", (256, 1)),
+]
+
+
+@pytest.mark.parametrize("name,npart,n,p,mode,drag,shape", STAGED_CASES)
+def test_interleaved_staged_step_is_bitwise_the_split_step(name, npart, n, p, mode, drag,
+                                                           shape):
+    """Migration after each RK2 stage (Sect. 3.2.2): the mid-step pool and
+    buffers and the final pool and buffers, bit for bit."""
+    say(f"[test] interleaved staged step {name} {mode} {drag} {shape}")
+    c = Case(name, npart, n, p, mode=mode, drag=drag, face=0.2, edge=0.05, corner=0.03)
+    c.params = pm.Params(min(c.dt, 0.015), c.g, drag=drag)
+    fi = interleaved(c.field)
+    res = []
+    for f in (c.field, fi):
+        pin, send = c.pin(), c.send()
+        pout = c.pout(pin.size)
+        mid = pm.DeviceStagePool.empty(c.host.base, c.host.cap, vdtype=c.vdt, device=c.dev,
+                                       size=pin.size)
+        msend = pm.DeviceStagePool.empty(c.sb, c.sc, vdtype=c.vdt, device=c.dev,
+                                         size=send.size)
+        ctx = c.ctx(pin, send)
+        ctx.set_tuning(*shape)
+        ctx.step_staged(f, c.dc, pin, mid, msend, pout, send, c.params)
+        assert ctx.get_status() == 0
+        res.append((pout, send, mid.to_host(), msend.to_host()))
+    assert_same_device_pools(res[0][0], res[1][0], c.dc.nsub, "out")
+    assert_same_device_pools(res[0][1], res[1][1], c.dc.nsub * 27, "send")
+    for k in (2, 3):
+        for name_ in ("x", "v", "xs", "vs", "a", "tau", "id", "count"):
+            np.testing.assert_array_equal(getattr(res[0][k], name_), getattr(res[1][k], name_),
+                                          err_msg=f"mid {name_}")
+
+
 def test_autotune_and_noalloc_on_an_interleaved_field():
     say("[test] interleaved autotune and noalloc, C2")
     c = Case("C2", 40000, 32, None)
@@ -173,8 +212,8 @@ def test_autotune_and_noalloc_on_an_interleaved_field():
 
 def test_interleaved_layout_argument_errors():
     """Rejected before any launch: an unknown layout, an interleaved MAC
-    field, u[1] or u[2] set on an interleaved field, and per-stage migration
-    on an interleaved field; a binding-built field of the wrong size."""
+    field, u[1] or u[2] set on an interleaved field; a binding-built field of
+    the wrong size."""
     say("[test] interleaved layout argument errors")
     c = Case("C1")
     fi = interleaved(c.field)
@@ -202,12 +241,6 @@ def test_interleaved_layout_argument_errors():
         with pytest.raises(pm.PMError):
             ctx.step(f, c.dc, pin, out, send, c.params)
         assert msg in pm.lib().pm_last_error(), pm.lib().pm_last_error()
-    mid = pm.DeviceStagePool.empty(c.host.base, c.host.cap, vdtype=c.vdt, device=c.dev,
-                                   size=pin.size)
-    mid_send = pm.DeviceStagePool.empty(c.sb, c.sc, vdtype=c.vdt, device=c.dev)
-    with pytest.raises(pm.PMError):
-        ctx.step_staged(fi, c.dc, pin, mid, mid_send, out, send, c.params)
-    assert b"per-stage" in pm.lib().pm_last_error()
     # the step is untouched by the rejected calls
     ctx.step(fi, c.dc, pin, out, send, c.params)
     assert ctx.get_status() == 0
