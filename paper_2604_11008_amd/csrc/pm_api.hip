@@ -682,8 +682,8 @@ pm_status pm_compact_append(pm_ctx *ctx, const pm_decomp *decomp, const pm_parti
                                   pm::kPrepCheckSend,
                            st),
            "prep launch");
-    PM_HIP(pm::launch_compact(k, sh, mixed, persistent_grid(ctx, sh, mixed, false, false, pm::kFieldSplit), st),
-           "compact launch");
+    const int cgrid = persistent_grid(ctx, sh, mixed, false, false, pm::kFieldSplit);
+    PM_HIP(pm::launch_compact(k, sh, mixed, cgrid, st), "compact launch");
     const int grid = std::min(4096, sub_count * k.cpt);
     PM_HIP(pm::launch_append(k, mixed, std::max(1, grid), st), "append launch");
     return PM_OK;
