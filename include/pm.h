@@ -105,8 +105,8 @@ typedef enum { PM_LAYOUT_SPLIT = 0, PM_LAYOUT_INTERLEAVED = 1 } pm_layout;
  *   of six values instead of three pairs from three arrays, which touches
  *   about half as many cache lines for isolated particles; the results are
  *   bitwise those of the split layout, through every entry point.  For
- *   solvers that can store the velocity this way: the library never
- *   converts a field.
+ *   solvers that can store the velocity this way, or for many steps on one
+ *   field, which pm_field_interleave copies once; no step converts a field.
  * stagger == 0: collocated, node (i,j,k) of every component at the cell
  * centre ((i+1/2)L0/n0, ...), as the paper interpolates (Sect. 2.2);
  * stagger == 1: MAC arrangement, as its fluid solver stores the velocity
@@ -270,6 +270,17 @@ pm_status pm_destroy(pm_ctx *ctx);
 pm_status pm_interp(pm_ctx *ctx, const pm_field *field, int64_t n,
                     const double *x, const double *y, const double *z,
                     void *ux, void *uy, void *uz, void *stream);
+
+/* The same field stored node-interleaved: writes the collocated split field
+ * `field` (layout PM_LAYOUT_SPLIT, stagger 0) into `out`, a device array of
+ * 3 x (stored nodes) values of the field's dtype, value 3m + c = component c
+ * of stored node m (PM_LAYOUT_INTERLEAVED; pass it as u[0] with u[1] = u[2] =
+ * NULL and the same n, halo, L and dtype).  For callers whose solver writes
+ * the split layout but who take many steps on one field: the copy reads and
+ * writes the field's bytes once each, and the interleaved steps are bitwise
+ * those on the split field.  `out` must not overlap the field.
+ * Asynchronous on `stream`; needs no context. */
+pm_status pm_field_interleave(const pm_field *field, void *out, void *stream);
 
 /* Steps 1-2 in place on the particles of segments [sub_first,
  * sub_first+sub_count): X and V are replaced by the Heun update.

@@ -45,6 +45,24 @@ pm_status hip_error(hipError_t e, const char *what)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// pm_field_interleave: one node per thread, the three components read from
+// their arrays and written next to each other (the node's 3 values are one
+// run of the output; a wave's stores cover consecutive runs).
+template <typename T>
+__global__ __launch_bounds__(256) void k_interleave(const T *__restrict__ u0,
+                                                    const T *__restrict__ u1,
+                                                    const T *__restrict__ u2,
+                                                    T *__restrict__ out, int64_t nodes)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nodes;
+         i += (int64_t)gridDim.x * 256) {
+        const T a = u0[i], b = u1[i], c = u2[i];
+        out[3 * i] = a;
+        out[3 * i + 1] = b;
+        out[3 * i + 2] = c;
+    }
+}
+
 struct WsLayout {
     size_t hdr, tile_start, stay, migtot, stg_start, lb, slot, stg, total;
     int64_t max_tiles, stg_extent;
@@ -564,6 +582,40 @@ pm_status pm_interp(pm_ctx *ctx, const pm_field *field, int64_t n, const double 
         return arg_error("NULL array");
     PM_HIP(pm::launch_interp(k, mixed, n, x, y, z, ux, uy, uz, (hipStream_t)stream),
            "interp launch");
+    return PM_OK;
+}
+
+pm_status pm_field_interleave(const pm_field *field, void *out, void *stream)
+{
+    pm::DField d;
+    bool mixed = false;
+    pm_status s = conv_field(field, d, mixed);
+    if (s)
+        return s;
+    if (field->layout != PM_LAYOUT_SPLIT || field->stagger)
+        return arg_error("pm_field_interleave takes a collocated field stored as one array "
+                         "per component");
+    if (!out)
+        return arg_error("out is NULL");
+    const int64_t nodes = d.sxy * (field->n[2] + 2 * field->halo);
+    const size_t elem = mixed ? sizeof(float) : sizeof(double);
+    const uintptr_t o0 = (uintptr_t)out, o1 = o0 + 3 * (size_t)nodes * elem;
+    for (int c = 0; c < 3; ++c) {
+        const uintptr_t a0 = (uintptr_t)field->u[c], a1 = a0 + (size_t)nodes * elem;
+        if (a0 < o1 && o0 < a1)
+            return arg_error("out overlaps field.u[%d]", c);
+    }
+    const int grid = (int)std::min<int64_t>(65536, std::max<int64_t>(1, (nodes + 255) / 256));
+    hipStream_t st = (hipStream_t)stream;
+    if (mixed)
+        hipLaunchKernelGGL(k_interleave<float>, dim3(grid), dim3(256), 0, st,
+                           (const float *)field->u[0], (const float *)field->u[1],
+                           (const float *)field->u[2], (float *)out, nodes);
+    else
+        hipLaunchKernelGGL(k_interleave<double>, dim3(grid), dim3(256), 0, st,
+                           (const double *)field->u[0], (const double *)field->u[1],
+                           (const double *)field->u[2], (double *)out, nodes);
+    PM_HIP(hipGetLastError(), "interleave launch");
     return PM_OK;
 }
 

@@ -186,6 +186,37 @@ def test_interleaved_staged_step_is_bitwise_the_split_step(name, npart, n, p, mo
                                           err_msg=f"mid {name_}")
 
 
+@pytest.mark.parametrize("halo,mixed", [(0, False), (1, False), (0, True), (1, True)])
+def test_library_interleave_copies_the_field(halo, mixed):
+    """pm_field_interleave writes exactly the stacked components (a copy, no
+    arithmetic), and a step on its output is bitwise the split step."""
+    say(f"[test] pm_field_interleave halo={halo} mixed={mixed}")
+    c = Case("C2" if halo else "C1", 30000, 24, None if halo else (2, 2, 2),
+             mode="mixed" if mixed else "f64")
+    assert c.wl.halo == halo
+    fi = pm.interleave_field(c.field)
+    torch.cuda.synchronize()
+    ref = torch.stack(c.field.u, dim=1).reshape(-1)
+    assert torch.equal(fi.u[0], ref)
+    # again into the same buffer, after spoiling it
+    fi.u[0].fill_(float("nan"))
+    pm.interleave_field(c.field, out=fi.u[0])
+    torch.cuda.synchronize()
+    assert torch.equal(fi.u[0], ref)
+    with pytest.raises(pm.PMError):
+        pm.interleave_field(c.field, out=fi.u[0][:-1])
+    pin = c.pin()
+    ctx = c.ctx(pin, c.send())
+    res = []
+    for f in (c.field, fi):
+        send, out = c.send(), c.pout(pin.size)
+        ctx.step(f, c.dc, pin, out, send, c.params)
+        assert ctx.get_status() == 0
+        res.append((out, send))
+    assert_same_device_pools(res[0][0], res[1][0], c.dc.nsub, "out")
+    assert_same_device_pools(res[0][1], res[1][1], c.dc.nsub * 27, "send")
+
+
 def test_autotune_and_noalloc_on_an_interleaved_field():
     say("[test] interleaved autotune and noalloc, C2")
     c = Case("C2", 40000, 32, None)
