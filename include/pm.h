@@ -273,14 +273,18 @@ pm_status pm_interp(pm_ctx *ctx, const pm_field *field, int64_t n,
 
 /* The same field stored node-interleaved: writes the collocated split field
  * `field` (layout PM_LAYOUT_SPLIT, stagger 0) into `out`, a device array of
- * 3 x (stored nodes) values of the field's dtype, value 3m + c = component c
- * of stored node m (PM_LAYOUT_INTERLEAVED; pass it as u[0] with u[1] = u[2] =
- * NULL and the same n, halo, L and dtype).  For callers whose solver writes
- * the split layout but who take many steps on one field: the copy reads and
- * writes the field's bytes once each, and the interleaved steps are bitwise
- * those on the split field.  `out` must not overlap the field.
+ * 3 x (stored nodes) values of type out_dtype (pm_dtype), value 3m + c =
+ * component c of stored node m (PM_LAYOUT_INTERLEAVED; pass it as u[0] with
+ * u[1] = u[2] = NULL and the same n, halo and L).  out_dtype is the field's
+ * dtype, or PM_F32 for a PM_F64 field: each value rounded to the nearest
+ * float, the field of the mixed mode written in the same pass.  For callers
+ * whose solver writes the split layout but who take many steps on one field,
+ * or who round it to float32 anyway: the pass reads and writes the field's
+ * bytes once each, and the interleaved steps are bitwise those on the split
+ * field of the same values.  `out` must not overlap the field.
  * Asynchronous on `stream`; needs no context. */
-pm_status pm_field_interleave(const pm_field *field, void *out, void *stream);
+pm_status pm_field_interleave(const pm_field *field, int32_t out_dtype, void *out,
+                              void *stream);
 
 /* Steps 1-2 in place on the particles of segments [sub_first,
  * sub_first+sub_count): X and V are replaced by the Heun update.

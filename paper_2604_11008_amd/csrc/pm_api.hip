@@ -46,17 +46,18 @@ pm_status hip_error(hipError_t e, const char *what)
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // pm_field_interleave: one node per thread, the three components read from
-// their arrays and written next to each other (the node's 3 values are one
-// run of the output; a wave's stores cover consecutive runs).
-template <typename T>
-__global__ __launch_bounds__(256) void k_interleave(const T *__restrict__ u0,
-                                                    const T *__restrict__ u1,
-                                                    const T *__restrict__ u2,
-                                                    T *__restrict__ out, int64_t nodes)
+// their arrays, converted to the output type (double to float rounds to
+// nearest) and written next to each other (the node's 3 values are one run
+// of the output; a wave's stores cover consecutive runs).
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_interleave(const Ti *__restrict__ u0,
+                                                    const Ti *__restrict__ u1,
+                                                    const Ti *__restrict__ u2,
+                                                    To *__restrict__ out, int64_t nodes)
 {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nodes;
          i += (int64_t)gridDim.x * 256) {
-        const T a = u0[i], b = u1[i], c = u2[i];
+        const To a = (To)u0[i], b = (To)u1[i], c = (To)u2[i];
         out[3 * i] = a;
         out[3 * i + 1] = b;
         out[3 * i + 2] = c;
@@ -585,7 +586,8 @@ pm_status pm_interp(pm_ctx *ctx, const pm_field *field, int64_t n, const double 
     return PM_OK;
 }
 
-pm_status pm_field_interleave(const pm_field *field, void *out, void *stream)
+pm_status pm_field_interleave(const pm_field *field, int32_t out_dtype, void *out,
+                              void *stream)
 {
     pm::DField d;
     bool mixed = false;
@@ -595,24 +597,33 @@ pm_status pm_field_interleave(const pm_field *field, void *out, void *stream)
     if (field->layout != PM_LAYOUT_SPLIT || field->stagger)
         return arg_error("pm_field_interleave takes a collocated field stored as one array "
                          "per component");
+    if (out_dtype != PM_F64 && out_dtype != PM_F32)
+        return arg_error("out_dtype must be PM_F64 or PM_F32");
+    if (mixed && out_dtype == PM_F64)
+        return arg_error("pm_field_interleave does not widen a PM_F32 field");
     if (!out)
         return arg_error("out is NULL");
     const int64_t nodes = d.sxy * (field->n[2] + 2 * field->halo);
-    const size_t elem = mixed ? sizeof(float) : sizeof(double);
-    const uintptr_t o0 = (uintptr_t)out, o1 = o0 + 3 * (size_t)nodes * elem;
+    const size_t ein = mixed ? sizeof(float) : sizeof(double);
+    const size_t eout = out_dtype == PM_F32 ? sizeof(float) : sizeof(double);
+    const uintptr_t o0 = (uintptr_t)out, o1 = o0 + 3 * (size_t)nodes * eout;
     for (int c = 0; c < 3; ++c) {
-        const uintptr_t a0 = (uintptr_t)field->u[c], a1 = a0 + (size_t)nodes * elem;
+        const uintptr_t a0 = (uintptr_t)field->u[c], a1 = a0 + (size_t)nodes * ein;
         if (a0 < o1 && o0 < a1)
             return arg_error("out overlaps field.u[%d]", c);
     }
     const int grid = (int)std::min<int64_t>(65536, std::max<int64_t>(1, (nodes + 255) / 256));
     hipStream_t st = (hipStream_t)stream;
     if (mixed)
-        hipLaunchKernelGGL(k_interleave<float>, dim3(grid), dim3(256), 0, st,
+        hipLaunchKernelGGL((k_interleave<float, float>), dim3(grid), dim3(256), 0, st,
                            (const float *)field->u[0], (const float *)field->u[1],
                            (const float *)field->u[2], (float *)out, nodes);
+    else if (out_dtype == PM_F32)
+        hipLaunchKernelGGL((k_interleave<double, float>), dim3(grid), dim3(256), 0, st,
+                           (const double *)field->u[0], (const double *)field->u[1],
+                           (const double *)field->u[2], (float *)out, nodes);
     else
-        hipLaunchKernelGGL(k_interleave<double>, dim3(grid), dim3(256), 0, st,
+        hipLaunchKernelGGL((k_interleave<double, double>), dim3(grid), dim3(256), 0, st,
                            (const double *)field->u[0], (const double *)field->u[1],
                            (const double *)field->u[2], (double *)out, nodes);
     PM_HIP(hipGetLastError(), "interleave launch");

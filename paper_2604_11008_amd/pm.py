@@ -103,7 +103,7 @@ def lib():
             "pm_step": ([vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "pm_step_staged": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "pm_step_noalloc": ([vp, vp, vp, vp, vp, vp, i64, i64, vp, vp], C.c_int),
-            "pm_field_interleave": ([vp, vp, vp], C.c_int),
+            "pm_field_interleave": ([vp, i32, vp, vp], C.c_int),
             "pm_get_status": ([vp, vp, vp], C.c_int),
             "pm_set_tuning": ([vp, vp], C.c_int),
             "pm_get_tuning": ([vp, vp], C.c_int),
@@ -529,18 +529,22 @@ def step_noalloc(field, decomp, pin, pout, send, params, flags, stream=None):
                                  _stream(stream)))
 
 
-def interleave_field(field, out=None, stream=None):
+def interleave_field(field, out=None, dtype=None, stream=None):
     """pm_field_interleave: the same field stored node-interleaved, written by
     the library into `out` (a contiguous device tensor of 3 x (stored nodes)
-    values of the field's dtype) or, if None, a new one."""
+    values) or, if None, a new one; dtype torch.float32 rounds a float64 field
+    (default: the field's own dtype)."""
     nodes = field.u[0].numel()
+    dtype = field.u[0].dtype if dtype is None else dtype
+    if dtype not in (torch.float64, torch.float32):
+        raise PMError("dtype must be torch.float64 or torch.float32")
     if out is None:
-        out = torch.empty((nodes, 3), dtype=field.u[0].dtype, device=field.u[0].device)
-    elif (out.numel() != 3 * nodes or out.dtype != field.u[0].dtype or
-          not out.is_contiguous()):
+        out = torch.empty((nodes, 3), dtype=dtype, device=field.u[0].device)
+    elif out.numel() != 3 * nodes or out.dtype != dtype or not out.is_contiguous():
         raise PMError("out must be a contiguous tensor of 3 values per stored node of the "
-                      "field's dtype")
-    _check(lib().pm_field_interleave(C.byref(field.c), _p(out), _stream(stream)))
+                      "requested dtype")
+    _check(lib().pm_field_interleave(C.byref(field.c), F64 if dtype == torch.float64 else F32,
+                                     _p(out), _stream(stream)))
     return DeviceField(out, field.n, field.halo, field.L, device=out.device, interleaved=True)
 
 

@@ -170,9 +170,9 @@ def test_binding_marshals_an_interleaved_field():
 
 def test_interleave_argument_errors_without_a_device():
     """pm_field_interleave checks its field and output before any launch: a
-    NULL field, a field already interleaved, a MAC field, a NULL output, and
-    an output overlapping a component (host tensors stand in for device
-    ones; no check reaches the device)."""
+    NULL field, a field already interleaved, a MAC field, a NULL output, an
+    output overlapping a component, an unknown output type and a widening
+    (host tensors stand in for device ones; no check reaches the device)."""
     import torch
     from paper_2604_11008_amd import pm
     lib = pm.lib()
@@ -181,18 +181,24 @@ def test_interleave_argument_errors_without_a_device():
     comps = [torch.zeros(nodes, dtype=torch.float64) for _ in range(3)]
     split = pm.DeviceField(comps, n, halo, 1.0, device="cpu")
     out = torch.zeros(3 * nodes, dtype=torch.float64)
-    assert lib.pm_field_interleave(None, out.data_ptr(), None) == 1
+    assert lib.pm_field_interleave(None, 0, out.data_ptr(), None) == 1
     assert b"field is NULL" in lib.pm_last_error()
     ilv = pm.DeviceField(out, n, halo, 1.0, device="cpu", interleaved=True)
-    assert lib.pm_field_interleave(ctypes.byref(ilv.c), out.data_ptr(), None) == 1
+    assert lib.pm_field_interleave(ctypes.byref(ilv.c), 0, out.data_ptr(), None) == 1
     assert b"one array per component" in lib.pm_last_error()
     mac = pm.DeviceField(comps, n, halo, 1.0, device="cpu", stagger=True)
-    assert lib.pm_field_interleave(ctypes.byref(mac.c), out.data_ptr(), None) == 1
+    assert lib.pm_field_interleave(ctypes.byref(mac.c), 0, out.data_ptr(), None) == 1
     assert b"one array per component" in lib.pm_last_error()
-    assert lib.pm_field_interleave(ctypes.byref(split.c), None, None) == 1
+    assert lib.pm_field_interleave(ctypes.byref(split.c), 0, None, None) == 1
     assert b"out is NULL" in lib.pm_last_error()
     big = torch.zeros(4 * nodes, dtype=torch.float64)
     shared = pm.DeviceField([big[:nodes], comps[1], comps[2]], n, halo, 1.0, device="cpu")
-    assert lib.pm_field_interleave(ctypes.byref(shared.c), big[nodes // 2:].data_ptr(),
+    assert lib.pm_field_interleave(ctypes.byref(shared.c), 0, big[nodes // 2:].data_ptr(),
                                    None) == 1
     assert b"overlaps field.u[0]" in lib.pm_last_error()
+    assert lib.pm_field_interleave(ctypes.byref(split.c), 2, out.data_ptr(), None) == 1
+    assert b"out_dtype" in lib.pm_last_error()
+    split32 = pm.DeviceField([c.float() for c in comps], n, halo, 1.0, device="cpu")
+    out32 = torch.zeros(3 * nodes, dtype=torch.float32)
+    assert lib.pm_field_interleave(ctypes.byref(split32.c), 0, out32.data_ptr(), None) == 1
+    assert b"does not widen" in lib.pm_last_error()

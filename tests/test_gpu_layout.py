@@ -186,21 +186,30 @@ def test_interleaved_staged_step_is_bitwise_the_split_step(name, npart, n, p, mo
                                           err_msg=f"mid {name_}")
 
 
-@pytest.mark.parametrize("halo,mixed", [(0, False), (1, False), (0, True), (1, True)])
-def test_library_interleave_copies_the_field(halo, mixed):
-    """pm_field_interleave writes exactly the stacked components (a copy, no
-    arithmetic), and a step on its output is bitwise the split step."""
-    say(f"[test] pm_field_interleave halo={halo} mixed={mixed}")
+@pytest.mark.parametrize("halo,kind", [(0, "f64"), (1, "f64"), (0, "f32"), (1, "f32"),
+                                       (0, "f64->f32"), (1, "f64->f32")])
+def test_library_interleave_copies_the_field(halo, kind):
+    """pm_field_interleave writes exactly the stacked components (a copy, or
+    from float64 the float32 values a cast gives), and a step on its output
+    is bitwise the split step on the same values."""
+    say(f"[test] pm_field_interleave halo={halo} {kind}")
     c = Case("C2" if halo else "C1", 30000, 24, None if halo else (2, 2, 2),
-             mode="mixed" if mixed else "f64")
+             mode="f64" if kind == "f64" else "mixed")
     assert c.wl.halo == halo
-    fi = pm.interleave_field(c.field)
+    if kind == "f64->f32":
+        src = pm.DeviceField(c.fh, c.wl.n, c.wl.halo, c.wl.L, device=c.dev)
+        fi = pm.interleave_field(src, dtype=torch.float32)
+    else:
+        fi = pm.interleave_field(c.field)
     torch.cuda.synchronize()
     ref = torch.stack(c.field.u, dim=1).reshape(-1)
     assert torch.equal(fi.u[0], ref)
     # again into the same buffer, after spoiling it
     fi.u[0].fill_(float("nan"))
-    pm.interleave_field(c.field, out=fi.u[0])
+    if kind == "f64->f32":
+        pm.interleave_field(src, out=fi.u[0], dtype=torch.float32)
+    else:
+        pm.interleave_field(c.field, out=fi.u[0])
     torch.cuda.synchronize()
     assert torch.equal(fi.u[0], ref)
     with pytest.raises(pm.PMError):
