@@ -699,7 +699,8 @@ def main():
     plain_on = args.plain == "on" or (args.plain == "auto" and precision == "both")
     args.first_mode = modes[0]
     # the interleaved runs from the same start: timed steps only (no samples,
-    # graph replay or plain path), in the split run's launch shape
+    # graph replay or plain path), in their own default launch shape (or the
+    # one --tune gives)
     ilv_args = argparse.Namespace(**vars(args))
     ilv_args.no_cpu = ilv_args.no_graph_replay = True
     ilv_args.cpu_delegated = ilv_args.migration_only = ilv_args.plain_per_sub = False
@@ -746,7 +747,6 @@ def main():
                 results[mode] = run(args, wl, dev, fi, dc, start, pool, sb, sc,
                                     mode == "mixed", plain_on and mode == "f64", mode)
             else:
-                ilv_args.tune = ",".join(str(v) for v in results[mode]["tuning"])
                 ilv_results[mode] = run(ilv_args, wl, dev, fi, dc, start, pool, sb, sc,
                                         mode == "mixed", False, f"{mode} interleaved")
                 ilv_results[mode]["interleave_ms"] = interleave_ms

@@ -123,18 +123,20 @@ def test_interleaved_step_matches_the_oracle():
     say(f"  migrants {int(ref_send.count.sum())}; max err x {ex:.2e} v {ev:.2e}")
 
 
-@pytest.mark.parametrize("mode", ["f64", "mixed"])
-def test_interleaved_step_in_the_timed_shape(mode):
+@pytest.mark.parametrize("mode,shape", [("f64", (256, 4)), ("mixed", (256, 2)),
+                                        ("mixed", (256, 4))])
+def test_interleaved_step_in_the_timed_shape(mode, shape):
     """The 1024^3 workload's recipe at 256^3 (2^22 blob-clustered particles,
-    8x8x8 subdomains) in its launch shape, 256 x 4, three steps in a row:
-    bitwise the split layout's pools after each."""
-    say(f"[test] interleaved timed shape {mode}, 256^3, 2^22 particles")
+    8x8x8 subdomains) in the launch shapes its interleaved runs are timed in
+    (256 x 4 at FP64, 256 x 2 mixed) and the split runs' 256 x 4, three steps
+    in a row: bitwise the split layout's pools after each."""
+    say(f"[test] interleaved timed shape {mode} {shape}, 256^3, 2^22 particles")
     c = Case("C5", npart=1 << 22, n=256, mode=mode, face=0.05, edge=0.01, corner=0.005)
     fi = interleaved(c.field)
     pa = [c.pin(), c.pin()]
     pb = [c.pout(pa[0].size), c.pout(pa[0].size)]
     ctx = c.ctx(pa[0], c.send())
-    ctx.set_tuning(256, 4)
+    ctx.set_tuning(*shape)
     for k in range(3):
         sends = []
         for j, f in enumerate((c.field, fi)):
