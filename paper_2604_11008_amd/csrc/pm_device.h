@@ -1089,6 +1089,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ?
             tau[k] = __builtin_nontemporal_load(&((const FT *)a.in.tau)[p]);
             id[k] = __builtin_nontemporal_load(&a.in.id[p]);
         }
+        // the stencil gathers are issued at a raised wave priority, so that a
+        // SIMD serves waves that can put requests into the L1's miss queue
+        // before waves in their scan or scatter (2-4% on the measured
+        // workloads, same results)
+        __builtin_amdgcn_s_setprio(3);
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             d[k] = 0xff;
@@ -1097,6 +1102,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ITEMS >= 8 ?
                 d[k] = classify(a.dc, own, X[k], fl);
             }
         }
+        __builtin_amdgcn_s_setprio(0);
 
         tile_ranks<WG, ITEMS>(C, d, rank);
         publish_aggregate<WG, ITEMS>(a, C);
