@@ -103,10 +103,12 @@ typedef enum { PM_LAYOUT_SPLIT = 0, PM_LAYOUT_INTERLEAVED = 1 } pm_layout;
  *   components next to each other (value 3m + c is component c of stored
  *   node m); u[1] and u[2] must be NULL.  A stencil row then takes one run
  *   of six values instead of three pairs from three arrays, which touches
- *   about half as many cache lines for isolated particles; the results are
- *   bitwise those of the split layout, through every entry point.  For
- *   solvers that can store the velocity this way, or for many steps on one
- *   field, which pm_field_interleave copies once; no step converts a field.
+ *   less than half as many 128-byte lines for isolated particles; the
+ *   results are bitwise those of the split layout, through every entry
+ *   point.  For solvers that can store the velocity this way, for many
+ *   steps on one field, or for the float32 field of the mixed mode, which
+ *   pm_field_interleave writes in one pass (a copy, or the rounding the
+ *   mixed mode needs anyway); no step converts a field.
  * stagger == 0: collocated, node (i,j,k) of every component at the cell
  * centre ((i+1/2)L0/n0, ...), as the paper interpolates (Sect. 2.2);
  * stagger == 1: MAC arrangement, as its fluid solver stores the velocity
