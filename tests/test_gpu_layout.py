@@ -291,3 +291,23 @@ def test_interleaved_layout_argument_errors():
     with pytest.raises(pm.PMError):
         pm.DeviceField(fi.u[0], fi.n, fi.halo, fi.L, device=c.dev, interleaved=True,
                        stagger=True)
+
+
+def test_geometry_calls_take_an_interleaved_field():
+    """pm_touched_nodes and pm_sort read only the field's grid: the same
+    count and the same re-sorted pool from either layout."""
+    say("[test] touched nodes and re-sort on an interleaved field")
+    c = Case("C3", 50000, 32, (4, 4, 4), order="shuffled")
+    fi = interleaved(c.field)
+    pin = c.pin()
+    ctx = c.ctx(pin, c.send())
+    ta = ctx.touched_nodes(c.field, pin, c.params)
+    tb = ctx.touched_nodes(fi, pin, c.params)
+    assert ta == tb > 0
+    outs = []
+    for f in (c.field, fi):
+        out = c.pout(pin.size)
+        ctx.sort(f, pin, out)
+        assert ctx.get_status() == 0
+        outs.append(out)
+    assert_same_device_pools(outs[0], outs[1], c.dc.nsub, "sorted")
