@@ -107,3 +107,22 @@ def test_torch_ordering_builds_the_same_pool(name, kw, order):
     b = gen.make_workload(name, order=order, sort_device="cpu", **kw)
     for f in ("x", "tau", "id", "base", "cap", "count"):
         np.testing.assert_array_equal(getattr(a.pool, f), getattr(b.pool, f), err_msg=f)
+
+
+def test_node_values_are_the_mode_sum_at_cell_centres():
+    """Each stored value is the real field sum over the generated modes,
+    2 Re(u_hat e^{i k.x}) per mode, evaluated at the cell centre (j + 1/2) h,
+    scaled to unit rms; by Parseval (all modes below Nyquist) the grid's mean
+    square before scaling is the sum of 2 |u_hat|^2."""
+    n, k0, kmax = 32, 2, 4
+    seed = gen.seeds(3)[0]
+    u = gen.spectral_field(n, k0, kmax, seed)
+    kv, uh = gen.spectral_modes(k0, kmax, seed)
+    scale = 1.0 / math.sqrt(sum(float((2 * np.abs(uh[:, c]) ** 2).sum()) for c in range(3)) / 3)
+    rng = np.random.default_rng(11)
+    ijk = rng.integers(0, n, (3, 200))
+    centres = (ijk + 0.5) * (2 * math.pi / n)
+    ph = np.exp(1j * (kv.astype(np.float64) @ centres))
+    for c in range(3):
+        exact = scale * 2 * np.real(uh[:, c] @ ph)
+        np.testing.assert_allclose(u[c][ijk[2], ijk[1], ijk[0]], exact, rtol=0, atol=1e-12)

@@ -136,3 +136,42 @@ def test_interpolant_is_continuous_across_cell_faces(halo):
     Ua, _ = oracle.interp(f, X - np.array([[eps], [0], [0]]))
     Ub, _ = oracle.interp(f, X + np.array([[eps], [0], [0]]))
     assert np.max(np.abs(Ua - Ub)) < 1e-6
+
+
+def test_spectral_field_is_approximated_to_second_order():
+    """On the generator's spectral field (cell-centre samples of a finite mode
+    sum) the interpolant approaches the continuous field: at every point the
+    error stays within the tensor-product bound of linear interpolation,
+    sum over axes of t_a (1 - t_a) h^2 / 2 max |d^2 u / dx_a^2| (t_a the
+    fraction of the cell below the point, the second derivative bounded by
+    the amplitudes times k_a^2), and halving the cell divides the rms error by
+    four.  A node convention off by any fraction of a cell leaves an error of
+    first order."""
+    from paper_2604_11008_amd import gen
+    k0, kmax = 2, 4
+    seed = gen.seeds(0)[0]
+    kv, uh = gen.spectral_modes(k0, kmax, seed)
+    kf = kv.astype(np.float64)
+    scale = 1.0 / np.sqrt(sum(float((2 * np.abs(uh[:, c]) ** 2).sum()) for c in range(3)) / 3)
+    L2 = 2 * np.pi
+    X = np.random.default_rng(7).uniform(0.0, L2, (3, 4000))
+    ph = np.exp(1j * (kf @ X))
+    exact = [scale * 2 * np.real(uh[:, c] @ ph) for c in range(3)]
+    d2max = [[scale * float((2 * np.abs(uh[:, c]) * kf[:, a] ** 2).sum()) for a in range(3)]
+             for c in range(3)]
+    rms = []
+    for n in (32, 64, 128):
+        h = L2 / n
+        f = oracle.Field([a.reshape(-1) for a in gen.spectral_field(n, k0, kmax, seed)], n, 0, L2)
+        U, flags = oracle.interp(f, X)
+        assert flags == 0
+        t = np.mod(X / h - 0.5, 1.0)
+        err = []
+        for c in range(3):
+            e = np.abs(U[c] - exact[c])
+            bound = sum(t[a] * (1 - t[a]) * h * h / 2 * d2max[c][a] for a in range(3))
+            assert np.all(e <= bound + 1e-13), (n, c, float(np.max(e / bound)))
+            err.append(np.sqrt(np.mean(e * e)))
+        rms.append(max(err))
+    for coarse, fine in zip(rms, rms[1:]):
+        assert 3.6 < coarse / fine < 4.4, rms
