@@ -224,8 +224,7 @@ typedef struct {
 
 /* Launch shape of the tile kernels: workgroup size (256 or 512), records
  * per thread (1, 2, 4 or 8); tile = wg*items records.  wg = 0 in
- * pm_set_tuning selects the per-variant defaults (256 x 4; 256 x 2 for FP64
- * periodic fields with the nonlinear drag law or the MAC arrangement, for
+ * pm_set_tuning selects the per-variant defaults (256 x 4; 256 x 2 for
  * mixed-precision periodic interleaved fields and for per-stage migration;
  * records per thread halved while the context's pool
  * extent gives fewer than two tiles per compute unit), which a context uses

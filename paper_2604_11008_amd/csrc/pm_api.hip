@@ -362,16 +362,13 @@ int auto_items(const pm_ctx *ctx, int max_items)
 }
 
 // Launch shape of a call: the tuned one, else a measured default — 256
-// threads x 4 records, except the FP64 periodic kernels with the nonlinear
-// drag law or a MAC field, whose 4-record variants run out of registers, and
-// the mixed periodic kernels on an interleaved field, 2-3% faster so on the
-// 1024^3 workload (x 2 records); fewer records per thread for small pools
-// (auto_items).
-pm::Shape shape_for(pm_ctx *ctx, bool mixed, bool halo, bool nonlinear, bool stagger,
-                    bool ilv = false)
+// threads x 4 records, except the mixed periodic kernels on an interleaved
+// field, 2-3% faster so on the 1024^3 workload (x 2 records); fewer records
+// per thread for small pools (auto_items).
+pm::Shape shape_for(pm_ctx *ctx, bool mixed, bool halo, bool ilv = false)
 {
     pm::Shape sh = ctx->shape;
-    const bool two = !halo && (mixed ? ilv : (nonlinear || stagger));
+    const bool two = !halo && mixed && ilv;
     if (ctx->shape_auto)
         sh = pm::Shape{256, auto_items(ctx, two ? 2 : 4)};
     ctx->last_shape = sh;
@@ -406,8 +403,7 @@ int append_cpt(int32_t count) { return std::max(1, 2048 / std::max(1, count)); }
 // Queue the fused step (prep, fused kernel, exchange) on `st`.
 pm_status queue_step(pm_ctx *ctx, pm::KArgs &k, bool mixed, hipStream_t st, bool timed)
 {
-    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0,
-                                 k.f.layout != 0);
+    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.f.layout != 0);
     k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(k.sub_count);
     PM_HIP(pm::launch_prep(k,
@@ -658,8 +654,7 @@ pm_status pm_interp_advance(pm_ctx *ctx, const pm_field *field, pm_particles *in
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = sub_first;
     k.sub_count = sub_count;
-    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0,
-                                 k.f.layout != 0);
+    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.f.layout != 0);
     k.tile = sh.wg * sh.items;
     PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn, st), "prep launch");
     const int grid =
@@ -699,7 +694,7 @@ pm_status pm_classify_scan_pack(pm_ctx *ctx, const pm_decomp *decomp, const pm_p
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = sub_first;
     k.sub_count = sub_count;
-    const pm::Shape sh = shape_for(ctx, mixed, false, false, false);
+    const pm::Shape sh = shape_for(ctx, mixed, false);
     k.tile = sh.wg * sh.items;
     PM_HIP(pm::launch_prep(k,
                            pm::kPrepTiles | pm::kPrepStaging | pm::kPrepZeroLb |
@@ -744,7 +739,7 @@ pm_status pm_compact_append(pm_ctx *ctx, const pm_decomp *decomp, const pm_parti
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = sub_first;
     k.sub_count = sub_count;
-    const pm::Shape sh = shape_for(ctx, mixed, false, false, false);
+    const pm::Shape sh = shape_for(ctx, mixed, false);
     k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(sub_count);
     PM_HIP(pm::launch_prep(k, pm::kPrepTiles | pm::kPrepCheckIn | pm::kPrepCheckOut |
@@ -882,8 +877,7 @@ pm_status pm_step(pm_ctx *ctx, const pm_field *field, const pm_decomp *decomp,
         return queue_step(ctx, k, mixed, st, timed);
     }
     // graph path: one captured graph per distinct argument set and shape
-    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0,
-                                 k.f.layout != 0);
+    const pm::Shape sh = shape_for(ctx, mixed, k.f.halo != 0, k.f.layout != 0);
     k.tile = sh.wg * sh.items;
     k.cpt = append_cpt(k.sub_count);
     return run_captured(ctx, graph_key(ctx, 'P', &k, 1, sh), st, [&](hipStream_t cs) {
@@ -1174,8 +1168,7 @@ pm_status pm_autotune(pm_ctx *ctx, const pm_field *field, const pm_decomp *decom
     PM_HIP(hipEventCreate(&guard.e0), "event create");
     PM_HIP(hipEventCreate(&guard.e1), "event create");
     float best = 1e30f;
-    pm::Shape best_sh = shape_for(ctx, mixed, k.f.halo != 0, k.drag != 0, k.f.stagger != 0,
-                                 k.f.layout != 0);
+    pm::Shape best_sh = shape_for(ctx, mixed, k.f.halo != 0, k.f.layout != 0);
     int best_bpc = ctx->blocks_per_cu;
     ctx->shape_auto = false;  // the sweep sets the shape of every trial
     for (const auto &sh : shapes) {
@@ -1340,7 +1333,7 @@ pm_status pm_touched_nodes(pm_ctx *ctx, const pm_field *field, const pm_particle
     hipStream_t st = (hipStream_t)stream;
     k.sub_first = 0;
     k.sub_count = in->nsub;
-    const pm::Shape sh = shape_for(ctx, mixed, false, false, false);
+    const pm::Shape sh = shape_for(ctx, mixed, false);
     k.tile = sh.wg * sh.items;
     const int64_t words = (nbits + 63) / 64;
     PM_HIP(pm::launch_fill(bitmap, words, st), "fill launch");

@@ -93,10 +93,10 @@ def test_bad_drag_parameters_are_argument_errors():
 
 
 def test_default_launch_shape_follows_the_variant():
-    """256 x 4 by default, 256 x 2 for the FP64 periodic nonlinear-drag (and
-    MAC) kernels, whose 4-record variants run out of registers; fewer
-    records per thread when the context's pool extent gives fewer than two
-    tiles per compute unit."""
+    """256 x 4 by default for either drag law (256 x 2 only for the mixed
+    kernels on an interleaved periodic field); a set shape until it is reset;
+    fewer records per thread when the context's pool extent gives fewer than
+    two tiles per compute unit."""
     from paper_2604_11008_amd import pm
     say("[test] per-variant default shapes")
     c = Case("C3", 50000, 32, (4, 4, 4), drag="nonlinear")
@@ -108,7 +108,7 @@ def test_default_launch_shape_follows_the_variant():
     pout = c.pout(extent)
     big = pm.Context(extent, send.size, c.dc.nsub, device=c.dev)
     big.step(c.field, c.dc, pin, pout, send, c.params)
-    assert big.get_tuning()[:2] == (256, 2)
+    assert big.get_tuning()[:2] == (256, 4)
     big.step(c.field, c.dc, pin, pout, send, stokes)
     assert big.get_tuning()[:2] == (256, 4)
     big.set_tuning(256, 1)
@@ -116,7 +116,7 @@ def test_default_launch_shape_follows_the_variant():
     assert big.get_tuning()[:2] == (256, 1)
     big.set_tuning(0, 0)
     big.step(c.field, c.dc, pin, pout, send, c.params)
-    assert big.get_tuning()[:2] == (256, 2)
+    assert big.get_tuning()[:2] == (256, 4)
     assert big.get_status() == 0
     # the unpadded pool (about 1.2e5 records) gives fewer than two
     # 256-record tiles per CU
@@ -126,3 +126,30 @@ def test_default_launch_shape_follows_the_variant():
     small.step(c.field, c.dc, spin, spout, send, stokes)
     assert small.get_tuning()[:2] == (256, 1)
     assert small.get_status() == 0
+
+
+@pytest.mark.parametrize("drag,stagger", [("nonlinear", False), ("stokes", True)])
+def test_periodic_variants_in_their_default_shape(drag, stagger):
+    """The FP64 periodic nonlinear-drag and MAC kernels at 256 x 4 (their
+    default for a large pool) against the oracle, and bitwise equal to 256 x 2,
+    on a pool of many tiles per segment."""
+    say(f"[test] periodic default shape drag={drag} stagger={stagger}")
+    c = Case("C3", 600000, 64, (4, 4, 4), drag=drag, stagger=stagger)
+    pin = c.pin()
+    ctx = c.ctx(pin, c.send())
+    outs = []
+    for shape in ((256, 4), (256, 2)):
+        ctx.set_tuning(*shape)
+        send, pout = c.send(), c.pout(pin.size)
+        ctx.step(c.field, c.dc, pin, pout, send, c.params)
+        assert ctx.get_status() == 0
+        assert tuple(ctx.get_tuning()[:2]) == shape
+        outs.append((pout, send))
+    assert_same_device_pools(outs[0][0], outs[1][0], c.dc.nsub, "out 256x4 vs 256x2")
+    assert_same_device_pools(outs[0][1], outs[1][1], c.dc.nsub * 27, "send 256x4 vs 256x2")
+    ref_out, ref_send, _, oflags = c.oracle_step()
+    assert oflags == 0
+    delta = c.wl.L / c.wl.n
+    compare_pools(outs[0][1].to_host(), ref_send, c.dc.nsub * 27, c.wl.L, delta, what="send")
+    ex, ev = compare_pools(outs[0][0].to_host(), ref_out, c.dc.nsub, c.wl.L, delta, what="out")
+    say(f"  migrants {int(ref_send.count.sum())}; max err x {ex:.2e} v {ev:.2e}")
