@@ -1,7 +1,8 @@
-"""The benchmark's check that an interleaved-field run ends on the split
-run's state compares 64-bit digests of the pools' valid records: the digest
-must change with any bit of a valid record or their order, and not with
-anything outside the valid records (host tensors stand in for device ones)."""
+"""Host-side parts of the benchmark.  Its check that an interleaved-field run
+ends on the split run's state compares 64-bit digests of the pools' valid
+records: the digest must change with any bit of a valid record or their
+order, and not with anything outside the valid records (host tensors stand
+in for device ones).  It measures one GPU and refuses more."""
 import importlib.util
 import os
 import types
@@ -54,3 +55,15 @@ def test_digest_sees_valid_records_only():
         q.v[:, 27] = 1.0
         q.id[29] = -1
         assert b.state_digest(q) == d0
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    """bench.py measures one GPU; --gpus above 1 exits before touching a
+    device, with a message that says so."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and "--gpus 2" in r.stderr
+    assert r.stdout == ""
